@@ -1,0 +1,202 @@
+/*
+ * ckks_lt.h - C interface of the MI355X (gfx950) library for homomorphic
+ * plaintext-matrix x encrypted-vector linear transformations (HE-LT) in
+ * RNS-CKKS, by the triple-hoisted baby-step giant-step algorithm
+ * (Akherati & Zhang, arXiv 2605.17222, Algorithm 2 and eq. (6)) and by the
+ * plain BSGS algorithm it is compared with (eq. (5), Table I).
+ *
+ * Every call takes plain pointers and sizes.  Pointers documented as "device"
+ * point to GPU memory on the device that was current when the parameter set
+ * was created; "host" pointers are read before the call returns.  Calls that
+ * take a `stream` (a hipStream_t; NULL = the default stream) only enqueue
+ * work and return without waiting: the caller keeps every buffer alive and
+ * unmodified until the stream has completed.  No call throws; errors are
+ * negative return codes, described by ckks_strerror().
+ *
+ * Data layout (fixed conventions, also followed by the test oracle):
+ *  - A limb is the N residues of one polynomial modulo one prime, stored as N
+ *    little-endian uint64 words, canonical in [0, q) (the [.]_q of eq. (3)).
+ *  - A polynomial over several primes is its limbs back to back: [limbs][N].
+ *  - Limbs are in NTT form, bit-reversed order (Section V, layout of
+ *    eq. (8)): word p of a limb holds sum_k a_k psi^((2 br(p)+1) k) mod q, with
+ *    br = bit reversal over log2 N bits and psi the primitive 2N-th root of
+ *    unity of that prime (see ckks_params_desc.psi).
+ *  - PQ-basis polynomials list the special primes first:
+ *    [p_0 .. p_{alpha-1}, q_0 .. q_l] (eq. (4) indexes q_j as limb j+alpha).
+ *    Truncating to a lower level keeps a prefix of that layout.
+ *  - Rotation r uses the Galois element g_r = 5^(r mod N/2) mod 2N
+ *    (Section II-A, eq. (2)); slots move toward slot 0.
+ */
+#ifndef CKKS_LT_H
+#define CKKS_LT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define CKKS_OK 0
+#define CKKS_E_INVALID_ARG -1  /* null pointer, bad size, level or split      */
+#define CKKS_E_UNSUPPORTED -2  /* missing rotation key, unsupported shape     */
+#define CKKS_E_WORKSPACE -3    /* workspace smaller than ckks_*_workspace_size */
+#define CKKS_E_DEVICE -4       /* a HIP runtime call failed                   */
+#define CKKS_E_NOMEM -5        /* device allocation failed                    */
+
+/* Text for an error code (static storage). */
+const char* ckks_strerror(int code);
+
+/* ---- parameter sets ---------------------------------------------------- */
+/*
+ * RNS-CKKS parameters (Section II-A): ring Z[X]/(X^N + 1), ciphertext modulus
+ * Q = q_0 ... q_L, special modulus P = p_0 ... p_{alpha-1} for the
+ * generalized key switching of Fig. 1, with alpha = ceil((L+1)/dnum).
+ */
+typedef struct {
+  int log_n;            /* log2 N, 8 <= log_n <= 16                          */
+  int n_q;              /* L + 1                                             */
+  const uint64_t* q;    /* host [n_q]: q_0 .. q_L                            */
+  int n_p;              /* alpha; must equal ceil(n_q / dnum)                */
+  const uint64_t* p;    /* host [n_p]: p_0 .. p_{alpha-1}                    */
+  int dnum;             /* number of key-switching digits at the top level   */
+  const uint64_t* psi;  /* host [n_p + n_q] (P first) primitive 2N-th roots,
+                           or NULL: then psi = g^((q-1)/2N) for the smallest
+                           quadratic non-residue g >= 2 of each prime        */
+} ckks_params_desc;
+
+typedef struct ckks_params ckks_params;  /* opaque, immutable once created */
+
+/*
+ * Validates the primes (prime, distinct, = 1 mod 2N, < 2^61, and for every
+ * basis conversion the sum of the source primes below 2^64) and builds the
+ * twiddle and RNS-constant tables in device memory on the current device.
+ * The library owns *out (free it with ckks_params_destroy).  It may be used
+ * from several streams at once.  Returns CKKS_OK or a negative code.
+ */
+int ckks_params_create(const ckks_params_desc* desc, ckks_params** out);
+void ckks_params_destroy(ckks_params* params);
+
+/* N, L and alpha of a parameter set (any pointer may be NULL). */
+void ckks_params_info(const ckks_params* params, int* log_n, int* n_q, int* n_p);
+
+/* ---- ciphertexts, plaintext diagonals, rotation keys --------------------- */
+typedef struct {
+  int level;     /* l: the ciphertext has l+1 limbs per polynomial           */
+  double scale;  /* CKKS scale, tracked only                                 */
+  uint64_t* c0;  /* device [l+1][N], NTT form                                */
+  uint64_t* c1;  /* device [l+1][N], NTT form                                */
+} ckks_ct;
+
+/*
+ * The diagonals of the LT matrix as NTT-form plaintexts (Section II-B).
+ * Diagonal index m = n1 n2 k + n1 j + i (TH-BSGS) or n1 j + i (BSGS) or the
+ * offset itself (diagonal method).  Plaintext m must already carry the
+ * giant-step pre-rotation of Algorithm 2's input list:
+ *   TH-BSGS : f^_m = phi_{-n1 n2 k}(f_m), PQ basis [alpha + L + 1][N]
+ *   BSGS    : f^_m = phi_{-n1 j}(f_m),    Q basis  [L + 1][N]
+ *   naive   : f_m,                        Q basis  [L + 1][N]
+ * A NULL pointer is an all-zero diagonal and is skipped exactly.
+ */
+typedef struct {
+  int n1, n2, n3;                /* split; n3 = 1 for BSGS; ignored by naive */
+  int n_diag;                    /* entries in pt                            */
+  const uint64_t* const* pt;     /* host [n_diag] of device pointers          */
+  double pt_scale;               /* scale the plaintexts were encoded with   */
+} ckks_lt_diags;
+
+/*
+ * Pre-rotated switching keys swk~_r = phi_{-r}(swk_r) (Algorithm 2, input
+ * list).  Key r is [beta_max][2][alpha + L + 1][N] words with
+ * beta_max = ceil((L+1)/alpha); polynomial 0 of digit b multiplies the digit
+ * and is added to c0, polynomial 1 forms the new c1.  Keys are generated at
+ * the top level and truncated by prefix for lower levels.
+ */
+typedef struct {
+  int count;
+  const int32_t* rot;          /* host [count]: r (taken mod N/2)           */
+  const uint64_t* const* key;  /* host [count] of device pointers           */
+} ckks_rotkeys;
+
+/* ---- the linear transformation ----------------------------------------- */
+#define CKKS_LT_NAIVE 0    /* diagonal method: sum_d Rot(ct, d) f_d           */
+#define CKKS_LT_BSGS 1     /* plain BSGS, eq. (5), one Decompose per rotation */
+#define CKKS_LT_TH_BSGS 2  /* triple-hoisted BSGS, Algorithm 2                */
+
+/* Workspace bytes ckks_lt_eval needs for this level, split and algorithm. */
+int ckks_lt_workspace_size(const ckks_params* params, int level, const ckks_lt_diags* diags, int algo,
+                           size_t* bytes);
+
+/*
+ * out = LT(in): enqueues the whole transformation on `stream`.
+ *   TH-BSGS follows Algorithm 2 (the final line is one ModDown by P q_l,
+ *   i.e. ModDown and rescale combined); BSGS and the diagonal method rotate
+ *   with Rot(ct, r) = (phi_r(c0 + x), phi_r(y)), (x, y) =
+ *   ModDown(<Decompose(c1), swk~_r>), and end with the rescale of eq. (1).
+ * in->level = l >= 1; out must have level l-1 buffers (l limbs) and must not
+ * alias in.  out->level and out->scale are set (scale = in.scale *
+ * pt_scale / q_l).  ws: device workspace of ws_bytes >= ckks_lt_workspace_size.
+ * Errors: CKKS_E_INVALID_ARG (nulls, level < 1, n_diag larger than the split,
+ * aliasing), CKKS_E_UNSUPPORTED (a needed rotation key is missing),
+ * CKKS_E_WORKSPACE, CKKS_E_DEVICE.
+ */
+int ckks_lt_eval(const ckks_params* params, const ckks_ct* in, const ckks_lt_diags* diags,
+                 const ckks_rotkeys* keys, int algo, ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- the steps of the path, one call each (for tests and composition) ---- */
+/*
+ * Negacyclic NTT (forward != 0) or inverse NTT of n_limbs limbs whose primes
+ * are the consecutive PQ indices first_prime .. first_prime + n_limbs - 1
+ * (0 .. alpha-1 are p_i, alpha + j is q_j).  in/out: device [n_limbs][N];
+ * in == out is allowed.  The inverse includes the factor N^-1.
+ */
+int ckks_op_ntt(const ckks_params* params, int forward, int first_prime, int n_limbs, const uint64_t* in,
+                uint64_t* out, void* stream);
+
+/*
+ * Decompose (Fig. 1; eq. (3)): x is a level-l Q-basis polynomial (device
+ * [l+1][N], NTT form); digits receives device [beta_l][alpha+l+1][N]
+ * (beta_l = ceil((l+1)/alpha)): digit b holds the group q_{alpha b} ..
+ * q_{min(alpha b + alpha - 1, l)} unchanged and its ModUp (basis conversion
+ * of the coefficient-domain group) in every other PQ limb.
+ * ws: device workspace >= ckks_op_workspace_size(params, l).
+ */
+int ckks_op_decompose(const ckks_params* params, int level, const uint64_t* x, uint64_t* digits, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/*
+ * ModDown (eq. (4)): x device [alpha+l+1][N] -> out device [l+1][N],
+ * out_j = P^-1 (x_{alpha+j} - BConv(x_P))_j mod q_j.
+ * If rescale != 0: ModDown by P q_l (ModDown and rescale combined, final
+ * line of Algorithm 2): out device [l][N].
+ */
+int ckks_op_moddown(const ckks_params* params, int level, int rescale, const uint64_t* x, uint64_t* out,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Rescale (eq. (1)): x device [l+1][N] -> out device [l][N]. */
+int ckks_op_rescale(const ckks_params* params, int level, const uint64_t* x, uint64_t* out, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Workspace bytes for the ckks_op_* calls at this level. */
+int ckks_op_workspace_size(const ckks_params* params, int level, size_t* bytes);
+
+/*
+ * Hoisted key-switch inner product with the automorphism applied on write
+ * (Algorithm 2, lines 4-5):  for the K = alpha+l+1 PQ limbs,
+ *   (x, y) = (sum_b d_b key_{b,0}, sum_b d_b key_{b,1}),
+ *   out_a = phi_r(add + x),  out_b = phi_r(y).
+ * digits: device [beta_l][K][N]; key: device [beta_max][2][alpha+L+1][N];
+ * add: device [K][N] or NULL (treated as zero); out_a, out_b: device [K][N].
+ */
+int ckks_op_keyswitch(const ckks_params* params, int level, const uint64_t* digits, const uint64_t* key,
+                      int32_t rot, const uint64_t* add, uint64_t* out_a, uint64_t* out_b, void* stream);
+
+/* NTT-domain automorphism phi_r (eq. (7)) of n_limbs limbs: out[p] = in[pi_r(p)]. */
+int ckks_op_automorph(const ckks_params* params, int32_t rot, int n_limbs, const uint64_t* in, uint64_t* out,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKKS_LT_H */

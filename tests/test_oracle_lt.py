@@ -1,0 +1,133 @@
+"""LT-level pins of the oracle: T3 (three algorithms agree), T4 (against FP64 M v),
+the operation counts stated in Section III / Table I, and special cases."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workload as W
+from _helpers import small_params
+
+
+@pytest.fixture(scope="module")
+def toy():
+    w = W.workload_toy()
+    o = O.Oracle(w.params)
+    o.keygen(101)
+    delta = 2.0 ** w.params.log_delta
+    ct = o.encrypt(w.level, w.vector, delta, seed=102)
+    rots = set(W.th_rotations(*w.th_split)) | set(W.bsgs_rotations(*w.bsgs_split)) | set(range(1, 16))
+    keys = o.rotkeys(sorted(rots))
+    return w, o, ct, keys, delta
+
+
+def _decode(o, out, w, delta):
+    scale = delta * delta / w.params.q[w.level]
+    return o.decrypt_slots(out, scale)
+
+
+def test_t3_t4_toy(toy):
+    w, o, ct, keys, delta = toy
+    ref = W.matvec(w.diags, w.vector)
+    th = o.lt_th(w.level, ct, w.th_split, o.th_plaintexts(w.diags, *w.th_split, delta), keys)
+    bs = o.lt_bsgs(w.level, ct, w.bsgs_split, o.bsgs_plaintexts(w.diags, *w.bsgs_split, delta), keys)
+    nv = o.lt_naive(w.level, ct, o.naive_plaintexts(w.diags, delta), keys)
+    zs = [_decode(o, x, w, delta) for x in (th, bs, nv)]
+    for z in zs:                                  # T4: <= 5e-3 at Delta = 2^30
+        assert np.abs(z - ref).max() <= 5e-3
+    for a in zs:                                  # T3: the three agree within tolerance
+        for b in zs:
+            assert np.abs(a - b).max() <= 5e-3
+    # different algorithms give different (equally valid) ciphertexts
+    assert not np.array_equal(th, bs)
+
+
+@pytest.mark.parametrize("split", [(2, 2, 4), (4, 2, 2), (1, 4, 4), (2, 8, 1), (16, 1, 1), (1, 1, 16)])
+def test_th_counts_match_text(toy, split):
+    # Section III: n1'+n3'-1 Decompose, n1'+n3' ModDown (final one counted once per
+    # polynomial) and n1'+n2'+n3'-3 switching keys.
+    w, o, ct, keys, delta = toy
+    n1, n2, n3 = split
+    o.reset_counters()
+    out = o.lt_th(w.level, ct, split, o.th_plaintexts(w.diags, n1, n2, n3, delta), keys)
+    c = o.counters()
+    if min(split) >= 2:
+        assert c["decompose"] == n1 + n3 - 1
+        assert c["moddown"] == n1 + n3
+    # degenerate splits skip the Decompose/ModDown whose output nothing uses
+    need_d0 = n1 > 1 or n2 > 1
+    assert c["decompose"] == int(need_d0) + (n1 - 1) * (n2 > 1) + (n3 - 1)
+    assert c["moddown"] == (n1 - 1) * (n2 > 1) + (n3 - 1) + 2
+    assert c["keys"] == n1 + n2 + n3 - 3
+    assert c["ks"] == n1 * n2 + n3 - 2
+    ref = W.matvec(w.diags, w.vector)
+    assert np.abs(_decode(o, out, w, delta) - ref).max() <= 5e-3
+
+
+@pytest.mark.parametrize("split", [(4, 4), (2, 8), (8, 2)])
+def test_bsgs_counts_match_table1(toy, split):
+    # Table I, row BSGS: n1+n2-2 Decompose, 2(n1+n2-2) ModDown, n1+n2-2 keys.
+    w, o, ct, keys, delta = toy
+    n1, n2 = split
+    o.reset_counters()
+    out = o.lt_bsgs(w.level, ct, split, o.bsgs_plaintexts(w.diags, n1, n2, delta), keys)
+    c = o.counters()
+    assert c["decompose"] == n1 + n2 - 2
+    assert c["moddown"] == 2 * (n1 + n2 - 2)
+    assert c["keys"] == n1 + n2 - 2
+    assert np.abs(_decode(o, out, w, delta) - W.matvec(w.diags, w.vector)).max() <= 5e-3
+
+
+def test_th_skips_zero_diagonals(toy):
+    # Absent diagonals are skipped exactly: a single diagonal at offset 5 needs
+    # only the keys on its own path and no outer-layer work.
+    w, o, ct, keys, delta = toy
+    diags = {5: w.diags[5]}
+    o.reset_counters()
+    out = o.lt_th(w.level, ct, (2, 2, 4), o.th_plaintexts(diags, 2, 2, 4, delta), keys)
+    c = o.counters()
+    assert c["keys"] == 2                     # rotations 1 and 4
+    assert c["decompose"] == 2 and c["moddown"] == 3
+    ref = W.matvec(diags, w.vector)
+    assert np.abs(_decode(o, out, w, delta) - ref).max() <= 5e-3
+
+
+def test_th_identity_and_diagonal_scaling(toy):
+    # The identity matrix (diagonal 0 all ones) reproduces the input slots.
+    w, o, ct, keys, delta = toy
+    S = w.params.slots
+    diags = {0: np.ones(S, dtype=complex)}
+    o.reset_counters()
+    out = o.lt_th(w.level, ct, (2, 2, 4), o.th_plaintexts(diags, 2, 2, 4, delta), keys)
+    assert np.abs(_decode(o, out, w, delta) - w.vector).max() <= 5e-3
+    c = o.counters()
+    assert c["decompose"] == 0 and c["keys"] == 0 and c["moddown"] == 2
+
+
+def test_th_lower_level(toy):
+    # Keys and plaintexts generated at the top level are truncated by prefix.
+    w, o, ct, keys, delta = toy
+    ct1 = o.encrypt(1, w.vector, delta, seed=7)
+    out = o.lt_th(1, ct1, w.th_split, o.th_plaintexts(w.diags, *w.th_split, delta), keys)
+    z = o.decrypt_slots(out, delta * delta / w.params.q[1])
+    assert np.abs(z - W.matvec(w.diags, w.vector)).max() <= 5e-3
+
+
+def test_th_multi_digit_groups():
+    # Unequal digit groups (alpha = 2, five q limbs, beta = 3) and negative
+    # effective rotations through the outer layer.
+    prm = small_params(8, nq=5, np_=2, dnum=3, bits_q=40, bits_p=52, log_delta=30, h=16)
+    prm = W.Params(log_n=8, q=(W.ntt_primes(50, 1, 512)[0],) + prm.q[1:], p=prm.p, dnum=3, log_delta=30, h=16)
+    o = O.Oracle(prm)
+    o.keygen(5)
+    S = prm.slots
+    diags = W.banded_diagonals(3, S, range(12))
+    v = W.input_vector(3, S)
+    delta = 2.0 ** 30
+    ct = o.encrypt(4, v, delta, seed=9)
+    keys = o.rotkeys(W.th_rotations(2, 2, 3) + W.bsgs_rotations(3, 4))
+    th = o.lt_th(4, ct, (2, 2, 3), o.th_plaintexts(diags, 2, 2, 3, delta), keys)
+    bs = o.lt_bsgs(4, ct, (3, 4), o.bsgs_plaintexts(diags, 3, 4, delta), keys)
+    ref = W.matvec(diags, v)
+    sc = delta * delta / prm.q[4]
+    assert np.abs(o.decrypt_slots(th, sc) - ref).max() <= 5e-3
+    assert np.abs(o.decrypt_slots(bs, sc) - ref).max() <= 5e-3
