@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark: homomorphic LT evaluations per second on one MI355X.
+
+Workload: one ciphertext at N = 2^16 (2^15 slots), level 24 (q0 of 60 bits,
+24 primes of 40 bits), alpha = 9 special primes of 60 bits, dnum = 3, times a
+banded matrix with 64 diagonals (offsets 0..63).  A step is one complete
+triple-hoisted BSGS LT (split (4,4,4), Algorithm 2) with inputs resident in
+HBM; the plain BSGS (8,8) LT on the same data is timed beside it.
+
+Inputs are seeded synthetic residues, uniform in [0, q) per limb: ciphertext,
+pre-rotated switching keys and NTT-form plaintext diagonals have exactly the
+shapes and value distribution (uniform residues in the NTT domain) of real
+ones, and the arithmetic does not depend on their values.  Bit-exactness on
+real keys and plaintexts is established by the parity tests, not here.
+
+Printed: one JSON line with LT/s, the roofline of the dominant kernel
+(measured with HIP events around its launches, on the launch stream, during
+the timed steps), and the CPU oracle timed on this host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CKKS LT evals/s and HBM GB/s at N=2^16, 64 diags; batched vs plain BSGS"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="a few steps, no baseline (for rocprofv3)")
+    return ap.parse_args()
+
+
+def make_inputs(P, prm, level, split, algo, seed, torch, H):
+    """Uniform residues on the device for the ciphertext, keys and plaintexts."""
+    import workload as W
+    n = prm.n
+    pq = list(prm.p) + list(prm.q)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+
+    def residues(moduli_rows):
+        m = torch.tensor(moduli_rows, dtype=torch.int64, device="cuda").view(-1, 1)
+        x = torch.randint(0, 2 ** 62, (len(moduli_rows), n), generator=g, dtype=torch.int64, device="cuda")
+        return torch.remainder(x, m)
+
+    qmods = [prm.q[j] for j in range(level + 1)]
+    c0, c1 = residues(qmods), residues(qmods)
+    kmax = prm.alpha + prm.max_level + 1
+    beta_max = -(-(prm.max_level + 1) // prm.alpha)
+    if algo == "th":
+        rots = W.th_rotations(*split)
+        pt_mods = pq[:kmax]
+        n_pt = split[0] * split[1] * split[2]
+    else:
+        rots = W.bsgs_rotations(*split)
+        pt_mods = list(prm.q)
+        n_pt = split[0] * split[1]
+    keys = {}
+    for r in rots:
+        keys[r] = residues(pq[:kmax] * (2 * beta_max)).view(beta_max, 2, kmax, n)
+    pts = [residues(pt_mods) for _ in range(n_pt)]
+    return c0, c1, keys, pts
+
+
+def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0):
+    c0, c1, keys, pts = make_inputs(P, prm, level, split, algo, 1234, torch, H)
+    code = H.CKKS_LT_TH_BSGS if algo == "th" else H.CKKS_LT_BSGS
+    ws_bytes = H.ckks_lt_workspace_size(P, level, split, pts, code)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out0 = H.empty((level, prm.n))
+    out1 = H.empty((level, prm.n))
+    delta = 2.0 ** prm.log_delta
+    stream = torch.cuda.current_stream()
+
+    def step():
+        H.ckks_lt_eval(P, level, delta, c0, c1, split, pts, delta, keys, code, out0, out1, ws, ws_bytes, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    H.ckks_profile_enable(profile_mask)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_events = ev0.elapsed_time(ev1)
+    prof = {}
+    if profile_mask:
+        for k, name in enumerate(H.KERNELS):
+            if profile_mask & (1 << k):
+                prof[name] = H.ckks_profile_read(k)
+        H.ckks_profile_enable(0)
+    return wall, ms_events, prof, ws_bytes
+
+
+def compulsory_bytes(prm, level, split, algo):
+    """Keys + plaintexts + ciphertext in and out, uint64 words (each read once)."""
+    import workload as W
+    n = prm.n
+    K = prm.alpha + level + 1
+    beta = -(-(level + 1) // prm.alpha)
+    if algo == "th":
+        nk = len(W.th_rotations(*split))
+        pt_limbs = K
+        npt = split[0] * split[1] * split[2]
+    else:
+        nk = len(W.bsgs_rotations(*split))
+        pt_limbs = level + 1
+        npt = split[0] * split[1]
+    words = nk * 2 * beta * K * n + npt * pt_limbs * n + 2 * (level + 1) * n + 2 * level * n
+    return words * 8
+
+
+def cpu_baseline(prm, level, split):
+    """The oracle's TH-BSGS LT on this host (keys and encoding excluded from timing)."""
+    import numpy as np
+    import oracle as O
+    import workload as W
+    w = W.workload_n16(level=level, th_split=split)
+    o = O.Oracle(w.params)
+    o.keygen(11)
+    delta = 2.0 ** w.params.log_delta
+    ct = o.encrypt(w.level, w.vector, delta, seed=5)
+    keys = o.rotkeys(W.th_rotations(*split))
+    pts = o.th_plaintexts(w.diags, *split, delta)
+    reps, t_total = 0, 0.0
+    while reps < 3 and t_total < 10.0:
+        t0 = time.perf_counter()
+        out = o.lt_th(w.level, ct, split, pts, keys)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    err = float(np.abs(o.decrypt_slots(out, delta * delta / w.params.q[level]) - W.matvec(w.diags, w.vector)).max())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": reps / t_total, "unit": "LT/s", "cores": threads, "kind": "oracle",
+            "sample": "%d full TH-BSGS (4,4,4) LT(s) at N=2^16, level 24, 64 diagonals, real keys; "
+                      "keygen/encoding excluded; decrypted max err %.1e" % (reps, err)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2605_17222_amd as H
+    import workload as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    H.lib()
+    prm = W.params_n16()
+    level = 24
+    th_split, bs_split = (4, 4, 4), (8, 8)
+    P = H.ckks_params_create(prm.log_n, prm.q, prm.p, prm.dnum)
+    if args.profile_only:
+        time_lt(P, prm, level, th_split, "th", max(1, args.steps), 1, torch, H)
+        time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), 1, torch, H)
+        print("profile run done", flush=True)
+        return
+
+    all_mask = (1 << len(H.KERNELS)) - 1
+    # 1) clean timed run (the headline value)
+    wall, ms_ev, _, ws_bytes = time_lt(P, prm, level, th_split, "th", args.steps, args.warmup, torch, H)
+    ms_step = ms_ev / args.steps
+    lt_s = args.steps / wall
+    # 2) the same steps with per-kernel HIP events, to find the dominant kernel
+    wall_p, ms_ev_p, prof, _ = time_lt(P, prm, level, th_split, "th", args.steps, 1, torch, H, all_mask)
+    # 3) plain BSGS beside it
+    wall_b, ms_ev_b, _, _ = time_lt(P, prm, level, bs_split, "bsgs", max(3, args.steps // 2), 2, torch, H)
+    bs_ms = ms_ev_b / max(3, args.steps // 2)
+
+    dom = max(prof, key=lambda k: prof[k][1])
+    n_l, ms_l, bytes_l = prof[dom]
+    achieved = bytes_l / (ms_l * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches_per_step": n_l / args.steps, "avg_launch_us": round(ms_l / n_l * 1e3, 2),
+                "share_of_step": round(ms_l / ms_ev_p, 3)}
+    breakdown = {k: {"launches_per_step": v[0] / args.steps, "ms_per_step": round(v[1] / args.steps, 4),
+                     "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}
+                 for k, v in prof.items()}
+    comp = compulsory_bytes(prm, level, th_split, "th")
+    out = {
+        "metric": METRIC, "value": round(lt_s, 2), "unit": "LT/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "single ciphertext TH-BSGS LT, N=2^16, level 24, alpha 9, dnum 3, 64 diagonals, "
+                               "split (4,4,4)", "N": prm.n, "level": level, "n_diag": 64, "split": list(th_split)},
+        "effective_GB_per_s": round(comp * lt_s / 1e9, 1),
+        "compulsory_bytes_per_lt": comp,
+        "plain_bsgs": {"split": list(bs_split), "ms_per_lt": round(bs_ms, 4), "lt_per_s": round(1e3 / bs_ms, 2),
+                       "compulsory_bytes_per_lt": compulsory_bytes(prm, level, bs_split, "bsgs")},
+        "th_vs_bsgs_speedup": round(bs_ms / ms_step, 3),
+        "workspace_bytes": ws_bytes,
+        "roofline": roofline,
+        "kernels": breakdown,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prm, level, th_split)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,35 @@ int ckks_op_keyswitch(const ckks_params* params, int level, const uint64_t* digi
 int ckks_op_automorph(const ckks_params* params, int32_t rot, int n_limbs, const uint64_t* in, uint64_t* out,
                       void* stream);
 
+/* ---- kernel timing (benchmarks) ---------------------------------------- */
+/* Kernel identifiers: the forward NTT column / row passes, the inverse NTT
+ * row / column passes, basis conversion, key-switch inner product, plaintext
+ * multiply-accumulate and the automorphism gather. */
+#define CKKS_KERNEL_NTT_FWD_COL 0
+#define CKKS_KERNEL_NTT_FWD_ROW 1
+#define CKKS_KERNEL_NTT_INV_ROW 2
+#define CKKS_KERNEL_NTT_INV_COL 3
+#define CKKS_KERNEL_BCONV 4
+#define CKKS_KERNEL_KEYSWITCH 5
+#define CKKS_KERNEL_PTMAC 6
+#define CKKS_KERNEL_AUTOMORPH 7
+#define CKKS_KERNEL_COUNT 8
+
+/*
+ * Process-wide: for every kernel k with bit (1 << k) set in mask, each later
+ * launch is bracketed by two HIP events recorded on the stream it is launched
+ * on.  Passing 0 stops recording.  Every call discards earlier records.
+ */
+int ckks_profile_enable(int mask);
+
+/*
+ * Waits for the recorded events of `kernel` and returns the number of
+ * recorded launches, their summed duration in milliseconds and their summed
+ * algorithmic bytes (compulsory reads and writes of the launch: each input
+ * and output word once).
+ */
+int ckks_profile_read(int kernel, int* launches, double* total_ms, double* total_bytes);
+
 #ifdef __cplusplus
 }
 #endif

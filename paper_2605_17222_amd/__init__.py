@@ -1,0 +1,290 @@
+"""Python binding of libckks_lt.so, the MI355X library for homomorphic linear
+transformations in RNS-CKKS (triple-hoisted BSGS, Algorithm 2 of arXiv
+2605.17222, and the plain BSGS / diagonal methods it is compared with).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libckks_lt.so.  Device buffers are torch tensors (uint64 words held
+in int64 tensors on a ROCm device); streams are torch.cuda streams.  The
+functions keep the names and argument order of include/ckks_lt.h.  If the
+library is not built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libckks_lt.so")
+
+CKKS_OK = 0
+CKKS_E_INVALID_ARG = -1
+CKKS_E_UNSUPPORTED = -2
+CKKS_E_WORKSPACE = -3
+CKKS_E_DEVICE = -4
+CKKS_E_NOMEM = -5
+
+CKKS_LT_NAIVE = 0
+CKKS_LT_BSGS = 1
+CKKS_LT_TH_BSGS = 2
+
+EXPORTED = [
+    "ckks_strerror", "ckks_params_create", "ckks_params_destroy", "ckks_params_info",
+    "ckks_lt_workspace_size", "ckks_lt_eval", "ckks_op_ntt", "ckks_op_decompose", "ckks_op_moddown",
+    "ckks_op_rescale", "ckks_op_workspace_size", "ckks_op_keyswitch", "ckks_op_automorph",
+    "ckks_profile_enable", "ckks_profile_read",
+]
+
+KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
+           "automorph"]
+
+
+class CkksError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class ParamsDesc(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_int), ("n_q", ctypes.c_int), ("q", _u64p), ("n_p", ctypes.c_int),
+                ("p", _u64p), ("dnum", ctypes.c_int), ("psi", _u64p)]
+
+
+class Ct(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("scale", ctypes.c_double), ("c0", ctypes.c_void_p),
+                ("c1", ctypes.c_void_p)]
+
+
+class Diags(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("n_diag", ctypes.c_int),
+                ("pt", ctypes.POINTER(ctypes.c_void_p)), ("pt_scale", ctypes.c_double)]
+
+
+class RotKeys(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("rot", ctypes.POINTER(ctypes.c_int32)),
+                ("key", ctypes.POINTER(ctypes.c_void_p))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libckks_lt.so is not built (run paper_2605_17222_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ckks_strerror.restype = ctypes.c_char_p
+        L.ckks_strerror.argtypes = [ctypes.c_int]
+        L.ckks_params_create.argtypes = [ctypes.POINTER(ParamsDesc), ctypes.POINTER(ctypes.c_void_p)]
+        L.ckks_params_destroy.argtypes = [ctypes.c_void_p]
+        L.ckks_params_destroy.restype = None
+        L.ckks_params_info.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 3
+        L.ckks_params_info.restype = None
+        L.ckks_lt_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Diags), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_size_t)]
+        L.ckks_lt_eval.argtypes = [ctypes.c_void_p, ctypes.POINTER(Ct), ctypes.POINTER(Diags),
+                                   ctypes.POINTER(RotKeys), ctypes.c_int, ctypes.POINTER(Ct), ctypes.c_void_p,
+                                   ctypes.c_size_t, ctypes.c_void_p]
+        L.ckks_op_ntt.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]
+        L.ckks_op_decompose.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.ckks_op_moddown.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.ckks_op_rescale.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.ckks_op_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.ckks_op_keyswitch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        L.ckks_op_automorph.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+        L.ckks_profile_enable.argtypes = [ctypes.c_int]
+        L.ckks_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().ckks_strerror(code).decode()
+    except RuntimeError:
+        return "error %d" % code
+
+
+def _check(code: int, what: str):
+    if code != CKKS_OK:
+        raise CkksError(code, what)
+
+
+def _ptr(t) -> Optional[int]:
+    """Device address of a tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Params:
+    """Owns a ckks_params* created by ckks_params_create."""
+
+    def __init__(self, handle: int, log_n: int, q: Sequence[int], p: Sequence[int]):
+        self.handle = handle
+        self.log_n = log_n
+        self.n = 1 << log_n
+        self.q = tuple(q)
+        self.p = tuple(p)
+        self.alpha = len(p)
+        self.max_level = len(q) - 1
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                lib().ckks_params_destroy(ctypes.c_void_p(self.handle))
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return ctypes.c_void_p(self.handle)
+
+
+def ckks_params_create(log_n: int, q: Sequence[int], p: Sequence[int], dnum: int,
+                       psi: Optional[Sequence[int]] = None) -> Params:
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pa = (ctypes.c_uint64 * len(p))(*p)
+    psa = (ctypes.c_uint64 * len(psi))(*psi) if psi is not None else None
+    d = ParamsDesc(log_n, len(q), ctypes.cast(qa, _u64p), len(p), ctypes.cast(pa, _u64p), dnum,
+                   ctypes.cast(psa, _u64p) if psa is not None else None)
+    h = ctypes.c_void_p()
+    _check(lib().ckks_params_create(ctypes.byref(d), ctypes.byref(h)), "ckks_params_create")
+    return Params(h.value, log_n, q, p)
+
+
+def ckks_params_info(params: Params) -> Tuple[int, int, int]:
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib().ckks_params_info(params, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def _diags(split: Sequence[int], pts: Sequence, pt_scale: float):
+    n1, n2, n3 = (list(split) + [1, 1])[:3]
+    arr = (ctypes.c_void_p * max(1, len(pts)))(*[_ptr(x) for x in pts])
+    return Diags(n1, n2, n3, len(pts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), pt_scale), arr
+
+
+def _keys(keys: Optional[Dict[int, object]]):
+    keys = keys or {}
+    rots = sorted(keys)
+    r = (ctypes.c_int32 * max(1, len(rots)))(*rots)
+    k = (ctypes.c_void_p * max(1, len(rots)))(*[_ptr(keys[x]) for x in rots])
+    return RotKeys(len(rots), ctypes.cast(r, ctypes.POINTER(ctypes.c_int32)),
+                   ctypes.cast(k, ctypes.POINTER(ctypes.c_void_p))), (r, k)
+
+
+def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts: Sequence, algo: int) -> int:
+    d, keep = _diags(split, pts, 1.0)
+    out = ctypes.c_size_t()
+    _check(lib().ckks_lt_workspace_size(params, level, ctypes.byref(d), algo, ctypes.byref(out)),
+           "ckks_lt_workspace_size")
+    return out.value
+
+
+def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequence[int], pts: Sequence,
+                 pt_scale: float, keys: Optional[Dict[int, object]], algo: int, out0, out1, ws, ws_bytes: int,
+                 stream=None) -> Tuple[int, float]:
+    """Enqueue out = LT(in); returns (out level, out scale)."""
+    cin = Ct(level, scale, _ptr(c0), _ptr(c1))
+    cout = Ct(level - 1, 0.0, _ptr(out0), _ptr(out1))
+    d, keep1 = _diags(split, pts, pt_scale)
+    k, keep2 = _keys(keys)
+    _check(lib().ckks_lt_eval(params, ctypes.byref(cin), ctypes.byref(d), ctypes.byref(k), algo,
+                              ctypes.byref(cout), _ptr(ws), ws_bytes, _stream(stream)), "ckks_lt_eval")
+    return cout.level, cout.scale
+
+
+def ckks_op_ntt(params: Params, forward: bool, first_prime: int, n_limbs: int, x, out, stream=None):
+    _check(lib().ckks_op_ntt(params, 1 if forward else 0, first_prime, n_limbs, _ptr(x), _ptr(out),
+                             _stream(stream)), "ckks_op_ntt")
+
+
+def ckks_op_workspace_size(params: Params, level: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().ckks_op_workspace_size(params, level, ctypes.byref(out)), "ckks_op_workspace_size")
+    return out.value
+
+
+def ckks_op_decompose(params: Params, level: int, x, digits, ws, ws_bytes: int, stream=None):
+    _check(lib().ckks_op_decompose(params, level, _ptr(x), _ptr(digits), _ptr(ws), ws_bytes, _stream(stream)),
+           "ckks_op_decompose")
+
+
+def ckks_op_moddown(params: Params, level: int, rescale: bool, x, out, ws, ws_bytes: int, stream=None):
+    _check(lib().ckks_op_moddown(params, level, 1 if rescale else 0, _ptr(x), _ptr(out), _ptr(ws), ws_bytes,
+                                 _stream(stream)), "ckks_op_moddown")
+
+
+def ckks_op_rescale(params: Params, level: int, x, out, ws, ws_bytes: int, stream=None):
+    _check(lib().ckks_op_rescale(params, level, _ptr(x), _ptr(out), _ptr(ws), ws_bytes, _stream(stream)),
+           "ckks_op_rescale")
+
+
+def ckks_op_keyswitch(params: Params, level: int, digits, key, rot: int, add, out_a, out_b, stream=None):
+    _check(lib().ckks_op_keyswitch(params, level, _ptr(digits), _ptr(key), rot, _ptr(add), _ptr(out_a),
+                                   _ptr(out_b), _stream(stream)), "ckks_op_keyswitch")
+
+
+def ckks_op_automorph(params: Params, rot: int, n_limbs: int, x, out, stream=None):
+    _check(lib().ckks_op_automorph(params, rot, n_limbs, _ptr(x), _ptr(out), _stream(stream)),
+           "ckks_op_automorph")
+
+
+def ckks_profile_enable(mask: int):
+    _check(lib().ckks_profile_enable(mask), "ckks_profile_enable")
+
+
+def ckks_profile_read(kernel: int) -> Tuple[int, float, float]:
+    """(launches, total ms, total algorithmic bytes) recorded for one kernel."""
+    n, ms, b = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().ckks_profile_read(kernel, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
+           "ckks_profile_read")
+    return n.value, ms.value, b.value
+
+
+# ---- tensor helpers (host <-> device copies of uint64 words) -------------------
+
+def to_device(a, device="cuda"):
+    """numpy uint64 array -> int64 torch tensor on the device (same bits)."""
+    import numpy as np
+    import torch
+    a = np.ascontiguousarray(a)
+    assert a.dtype == np.uint64
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def to_host(t):
+    """int64 torch tensor -> numpy uint64 array (same bits)."""
+    import numpy as np
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def empty(shape, device="cuda"):
+    import torch
+    return torch.empty(shape, dtype=torch.int64, device=device)

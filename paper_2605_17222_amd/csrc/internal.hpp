@@ -1,0 +1,148 @@
+// Internal types shared by the host orchestration and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/ckks_lt.h"
+
+namespace ckks {
+
+constexpr int kMaxSrc = 16;    // basis-conversion source limbs
+constexpr int kMaxDst = 64;    // basis-conversion destination limbs (alpha + L + 1)
+constexpr int kMaxBeta = 8;    // key-switching digits
+constexpr int kMaxKs = 8;      // keys applied to one digit set per launch
+constexpr int kMaxMacM = 16;   // plaintext-MAC inputs per launch
+constexpr int kMaxMacK = 8;    // plaintext-MAC accumulators per launch
+
+// Per-prime constants, indexed by PQ index (special primes first).
+struct PrimeDev {
+  uint64_t q;
+  uint64_t qinv_neg;       // -q^-1 mod 2^64 (Montgomery REDC)
+  uint64_t r_lo, r_hi;     // floor(2^128 / q) (Barrett)
+  uint64_t ninv, ninv_sh;  // N^-1 mod q and its Shoup companion
+  uint64_t pmod, pmod_sh;  // P mod q (0 on the special primes) and companion
+  const uint64_t* tw;      // [4][N]: psi^br(i), Shoup, psi^-br(i), Shoup
+};
+
+// Basis conversion eq. (3) from `ns` source limbs to `nd` destination limbs,
+// plus the final factor S^-1 of a division step (eq. (4), eq. (1)).
+struct BConvPlan {
+  int ns, nd;
+  int src[kMaxSrc];                 // PQ indices, in the order of the source limbs
+  int dst[kMaxDst];                 // PQ indices
+  uint64_t hinv[kMaxSrc];           // (S/s_j)^-1 mod s_j
+  uint64_t hinv_sh[kMaxSrc];        // Shoup companion
+  uint64_t hmod[kMaxDst][kMaxSrc];  // [S/s_j]_{d_m} * 2^64 mod d_m
+  uint64_t sinv[kMaxDst];           // S^-1 mod d_m
+  uint64_t sinv_sh[kMaxDst];
+};
+
+// A run of `count` limbs stored back to back whose primes are consecutive PQ
+// indices starting at prime0.
+struct LimbRange {
+  const uint64_t* in;
+  uint64_t* out;
+  const uint64_t* aux;  // epilogue operand laid out like out (or null)
+  int prime0;
+  int count;
+  int epi0;             // plan index of the first limb's epilogue constant
+  int pad;
+};
+
+constexpr int kMaxRanges = 8;
+struct NttArgs {
+  int nr = 0;
+  LimbRange r[kMaxRanges];
+};
+
+// Epilogue of the last forward pass: ModDown / rescale division step
+// out = (aux - v) * S^-1 mod q.
+enum EpiMode { EPI_NONE = 0, EPI_SUBMUL = 1 };
+
+constexpr int kMaxConv = 8;
+struct BConvArgs {
+  const BConvPlan* plan[kMaxConv];
+  const uint64_t* src[kMaxConv];  // source limb j at src + j N
+  uint64_t* dst[kMaxConv];        // destination limb m at dst + (plan.dst[m] - dst_shift) N
+  int dst_shift[kMaxConv];
+  int limbs_moved;                // sum over items of ns + nd (timing only)
+};
+
+struct KsArgs {
+  const uint64_t* digits;  // [beta][K][N]
+  int beta, K, kmax;       // kmax: limb stride of the keys [beta_max][2][kmax][N]
+  int nkeys;
+  int add_pscaled;         // add is a Q-basis polynomial to be multiplied by P
+  int accumulate;          // out[dst] += value
+  const uint64_t* key[kMaxKs];
+  uint32_t gal_inv[kMaxKs];  // Galois element of -r: value at p is written to phi index of p
+  const uint64_t* add;       // [K][N] (or [K - alpha][N] if add_pscaled), may be null
+  uint64_t* out_a[kMaxKs];
+  uint64_t* out_b[kMaxKs];
+};
+
+struct MacArgs {
+  int nm, nk, K, prime_off;
+  int pscaled0;    // a[0], b[0] are Q-basis polynomials to be multiplied by P
+  int accumulate;  // add into the outputs
+  const uint64_t* a[kMaxMacM];
+  const uint64_t* b[kMaxMacM];
+  const uint64_t* f[kMaxMacK][kMaxMacM];  // null = absent diagonal
+  uint64_t* out0[kMaxMacK];
+  uint64_t* out1[kMaxMacK];
+};
+
+struct AutoArgs {
+  const uint64_t* in;
+  const uint64_t* add;  // may be null
+  uint64_t* out;
+  int nlimbs, prime_off, accumulate;
+  uint32_t gal;         // out[p] = (in + add)[auto_index(p, gal)]
+};
+
+// Brackets one launch with HIP events when its kernel is being timed.
+class ProfScope {
+ public:
+  ProfScope(int id, hipStream_t s, double bytes);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  int id_;
+  hipStream_t s_;
+  double bytes_;
+  void* a_ = nullptr;
+  void* b_ = nullptr;
+  bool active_ = false;
+};
+
+// Kernel launchers.
+hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
+                      const BConvPlan* epi_plan, hipStream_t s);
+hipError_t launch_bconv(const struct ::ckks_params* P, const BConvArgs& a, int items, hipStream_t s);
+hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipStream_t s);
+hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
+hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
+
+}  // namespace ckks
+
+struct ckks_params {
+  int device = 0;
+  int log_n = 0, n = 0;
+  int L = 0, alpha = 0, dnum = 0;
+  std::vector<uint64_t> primes;        // PQ order
+  ckks::PrimeDev* d_primes = nullptr;  // device [K_max]
+  uint64_t* d_tw = nullptr;            // device [K_max][4][N]
+  ckks::BConvPlan* d_plans = nullptr;  // device plan table
+  std::vector<int> plan_decomp;        // level * beta_max + b -> plan index
+  std::vector<int> plan_moddown, plan_mdrescale, plan_rescale;  // per level
+  int beta_max = 0;
+  int K(int level) const { return alpha + level + 1; }
+  int beta(int level) const { return (level + alpha) / alpha; }
+  int Kmax() const { return alpha + L + 1; }
+  const ckks::BConvPlan* plan(int idx) const { return d_plans + idx; }
+};

@@ -1,0 +1,160 @@
+// HBM-bound element-wise kernels of the LT:
+//  * hoisted key-switch inner product (x, y) = sum_b d_b (swk_b0, swk_b1)
+//    over the PQ limbs, several keys per digit read, with the add of
+//    Algorithm 2 lines 4/9/17 and the automorphism phi_r applied on write;
+//  * plaintext multiply-accumulate into several accumulators at once
+//    (Algorithm 2 lines 12 and 14);
+//  * NTT-domain automorphism as a gather (eq. (7)), with an optional add.
+//
+// The automorphism is written as a scatter: the value computed at position p
+// goes to phi's position of p, pi_{-r}(p).  Eq. (8) shows that an aligned
+// block of d_p positions maps onto one aligned block of d_p positions for any
+// power of two d_p, so a wavefront of 64 consecutive positions writes one
+// aligned 512-byte block: the stores stay coalesced.
+//
+// Products of two data operands are accumulated as exact 128-bit sums and
+// reduced once per output with Barrett's floor(2^128 / q); the number of terms
+// t satisfies t q^2 < 2^128 (the host splits larger sums).
+#include "internal.hpp"
+#include "modarith.hpp"
+
+namespace ckks {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void __launch_bounds__(kThreads)
+    ks_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
+  const size_t n = (size_t)1 << log_n;
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const PrimeDev& pr = primes[l];
+  const uint64_t q = pr.q;
+
+  uint64_t d[kMaxBeta];
+#pragma unroll
+  for (int b = 0; b < kMaxBeta; ++b)
+    if (b < a.beta) d[b] = a.digits[((size_t)b * a.K + l) * n + p];
+
+  uint64_t addv = 0;
+  if (a.add) {
+    if (a.add_pscaled)
+      addv = (l < alpha) ? 0 : shoup(a.add[(size_t)(l - alpha) * n + p], pr.pmod, pr.pmod_sh, q);
+    else
+      addv = a.add[(size_t)l * n + p];
+  }
+
+  for (int k = 0; k < a.nkeys; ++k) {
+    const uint64_t* __restrict__ key = a.key[k];
+    U128 x = {0, 0}, y = {0, 0};
+#pragma unroll
+    for (int b = 0; b < kMaxBeta; ++b) {
+      if (b < a.beta) {
+        add128(x, mul_wide(d[b], key[(((size_t)b * 2 + 0) * a.kmax + l) * n + p]));
+        add128(y, mul_wide(d[b], key[(((size_t)b * 2 + 1) * a.kmax + l) * n + p]));
+      }
+    }
+    const uint64_t xr = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
+    const uint64_t yr = barrett128(y, q, pr.r_lo, pr.r_hi);
+    const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
+    if (a.accumulate) {
+      a.out_a[k][o] = add_mod(a.out_a[k][o], xr, q);
+      a.out_b[k][o] = add_mod(a.out_b[k][o], yr, q);
+    } else {
+      a.out_a[k][o] = xr;
+      a.out_b[k][o] = yr;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    mac_kernel(MacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
+  const size_t n = (size_t)1 << log_n;
+  const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const PrimeDev& pr = primes[l + a.prime_off];
+  const uint64_t q = pr.q;
+  const size_t off = (size_t)l * n + p;
+
+  uint64_t av[kMaxMacM], bv[kMaxMacM];
+#pragma unroll
+  for (int m = 0; m < kMaxMacM; ++m) {
+    if (m < a.nm) {
+      if (m == 0 && a.pscaled0) {
+        // (a_0, b_0) = (P c0', P c1'): zero on the special primes.
+        const int lq = l + a.prime_off - alpha;
+        av[m] = lq < 0 ? 0 : shoup(a.a[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
+        bv[m] = lq < 0 ? 0 : shoup(a.b[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
+      } else {
+        av[m] = a.a[m][off];
+        bv[m] = a.b[m][off];
+      }
+    }
+  }
+  for (int k = 0; k < a.nk; ++k) {
+    U128 x = {0, 0}, y = {0, 0};
+#pragma unroll
+    for (int m = 0; m < kMaxMacM; ++m) {
+      if (m < a.nm && a.f[k][m]) {
+        const uint64_t f = a.f[k][m][off];
+        add128(x, mul_wide(av[m], f));
+        add128(y, mul_wide(bv[m], f));
+      }
+    }
+    uint64_t xr = barrett128(x, q, pr.r_lo, pr.r_hi);
+    uint64_t yr = barrett128(y, q, pr.r_lo, pr.r_hi);
+    if (a.accumulate) {
+      xr = add_mod(xr, a.out0[k][off], q);
+      yr = add_mod(yr, a.out1[k][off], q);
+    }
+    a.out0[k][off] = xr;
+    a.out1[k][off] = yr;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    auto_kernel(AutoArgs a, const PrimeDev* __restrict__ primes, int log_n) {
+  const size_t n = (size_t)1 << log_n;
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const uint64_t q = primes[l + a.prime_off].q;
+  const size_t s = (size_t)l * n + auto_index(p, a.gal, log_n);
+  uint64_t v = a.in[s];
+  if (a.add) v = add_mod(v, a.add[s], q);
+  const size_t o = (size_t)l * n + p;
+  if (a.accumulate) v = add_mod(v, a.out[o], q);
+  a.out[o] = v;
+}
+
+}  // namespace
+
+hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  const double words = (double)a.K * P->n *
+                       (a.beta + a.nkeys * (2.0 * a.beta + 2 + (a.accumulate ? 2 : 0)) + (a.add ? 1 : 0));
+  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * 8);
+  hipLaunchKernelGGL(ks_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_ptmac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  int nf = 0;
+  for (int k = 0; k < a.nk; ++k)
+    for (int m = 0; m < a.nm; ++m) nf += a.f[k][m] ? 1 : 0;
+  const double words = (double)a.K * P->n * (2.0 * a.nm + nf + 2.0 * a.nk * (a.accumulate ? 2 : 1));
+  ProfScope prof(CKKS_KERNEL_PTMAC, s, words * 8);
+  hipLaunchKernelGGL(mac_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_automorph(const ckks_params* P, const AutoArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.nlimbs);
+  ProfScope prof(CKKS_KERNEL_AUTOMORPH, s,
+                 (double)a.nlimbs * P->n * 8 * (2 + (a.add ? 1 : 0) + (a.accumulate ? 1 : 0)));
+  hipLaunchKernelGGL(auto_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  return hipGetLastError();
+}
+
+}  // namespace ckks

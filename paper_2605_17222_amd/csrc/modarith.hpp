@@ -1,0 +1,89 @@
+// 64-bit modular arithmetic on the gfx950 vector ALU.
+//
+// Residues are uint64 below primes q < 2^61.  There is no 64x64->128 multiply
+// instruction: a full product is four 32x32->64 multiply-adds
+// (v_mad_u64_u32).  Three reductions are used, each where it is cheapest:
+//  * Shoup multiplication by a constant w with w' = floor(w 2^64 / q) (NTT
+//    twiddles, scaling constants): result in [0, 2q).
+//  * Montgomery REDC of a 128-bit sum x < q 2^64 (basis conversion, whose
+//    constants are stored premultiplied by 2^64): x 2^-64 mod q.
+//  * Barrett reduction of any 128-bit value with floor(2^128 / q) (key-switch
+//    and plaintext inner products, whose operands are both data).
+// Lazy (non-canonical) intermediate ranges are documented at each use.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ckks {
+
+struct U128 {
+  uint64_t lo, hi;
+};
+
+// Full 64x64 -> 128 product from four 32x32 -> 64 multiply-adds.
+__host__ __device__ __forceinline__ U128 mul_wide(uint64_t a, uint64_t b) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);          // < 2^64
+  const uint64_t u = (uint64_t)a1 * b0 + (uint32_t)t;          // < 2^64
+  U128 r;
+  r.hi = (uint64_t)a1 * b1 + ((t >> 32) + (u >> 32));
+  r.lo = (u << 32) | (uint32_t)p00;
+  return r;
+}
+
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return mul_wide(a, b).hi; }
+
+__host__ __device__ __forceinline__ void add128(U128& acc, U128 v) {
+  acc.lo += v.lo;
+  acc.hi += v.hi + (acc.lo < v.lo ? 1 : 0);
+}
+
+__host__ __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) { return x >= q ? x - q : x; }
+
+__host__ __device__ __forceinline__ uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) { return csub(a + b, q); }
+__host__ __device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+
+// a * w mod q in [0, 2q) for any a < 2^64, w < q, wp = floor(w 2^64 / q).
+__host__ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  return a * w - mulhi64(a, wp) * q;
+}
+__host__ __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  return csub(shoup_lazy(a, w, wp, q), q);
+}
+
+// x 2^-64 mod q for x < q 2^64, qinv_neg = -q^-1 mod 2^64; result canonical.
+__host__ __device__ __forceinline__ uint64_t redc(U128 x, uint64_t q, uint64_t qinv_neg) {
+  const uint64_t m = x.lo * qinv_neg;
+  const uint64_t t = x.hi + mulhi64(m, q) + (x.lo != 0 ? 1 : 0);
+  return csub(t, q);
+}
+
+// x mod q for any x < 2^128, with (r_hi, r_lo) = floor(2^128 / q).
+// qhat = floor(x r / 2^128) satisfies x/q - 2 < qhat <= x/q, so x - qhat q is
+// in [0, 2q) and is computed modulo 2^64.
+__host__ __device__ __forceinline__ uint64_t barrett128(U128 x, uint64_t q, uint64_t r_lo, uint64_t r_hi) {
+  const uint64_t c0 = mulhi64(x.lo, r_lo);
+  const U128 p1 = mul_wide(x.lo, r_hi);
+  const U128 p2 = mul_wide(x.hi, r_lo);
+  uint64_t s = p1.lo + c0;
+  uint64_t carry = s < c0 ? 1 : 0;
+  s += p2.lo;
+  carry += s < p2.lo ? 1 : 0;
+  const uint64_t qhat = x.hi * r_hi + p1.hi + p2.hi + carry;
+  return csub(x.lo - qhat * q, q);
+}
+
+// Bit reversal of the low `bits` bits.
+__device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
+
+// NTT-domain automorphism index.  With g the Galois element, position p of
+// phi_g(a) holds a at position br((g (2 br(p) + 1) mod 2N - 1) / 2).
+__device__ __forceinline__ uint32_t auto_index(uint32_t p, uint32_t g, int log_n) {
+  const uint32_t l = bitrev(p, log_n);
+  const uint32_t e = (uint32_t)(((uint64_t)g * (2u * l + 1u)) & ((2u << log_n) - 1u));
+  return bitrev((e - 1u) >> 1, log_n);
+}
+
+}  // namespace ckks
