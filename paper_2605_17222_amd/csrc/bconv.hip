@@ -1,12 +1,15 @@
 // Basis conversion, eq. (3):  y_j = [(S/s_j)^-1 x_j]_{s_j},
 //                             out_m = sum_j y_j [S/s_j]_{d_m} mod d_m.
-// Coefficient-domain limbs; one thread per coefficient position, all source
-// limbs of that position in registers (the type-II dependency of Section IV:
-// every limb of a coefficient is needed).  The constants [S/s_j]_{d_m} are
-// stored times 2^64 mod d_m, so one Montgomery REDC of the 128-bit sum gives
-// the canonical result; this needs sum_j s_j <= 2^64, which parameter
-// creation checks.  Several conversions (the digits of Decompose) run in one
-// launch, one per blockIdx.y.
+// Coefficient-domain limbs; each thread owns one coefficient position with
+// all source limbs of that position in registers (the type-II dependency of
+// Section IV: every limb of a coefficient is needed).  The constants
+// [S/s_j]_{d_m} are stored times 2^64 mod d_m, so one Montgomery REDC of the
+// exact 128-bit sum gives the canonical result; this needs sum_j s_j <= 2^64,
+// which parameter creation checks.  The number of source limbs is a template
+// parameter so the inner product is fully unrolled and its constants come in
+// with wide scalar loads.  Several conversions (the digits of Decompose) run
+// in one launch, one per blockIdx.y; blockIdx.z splits the destination limbs
+// into chunks so that a launch has enough workgroups to fill 256 CUs.
 #include "internal.hpp"
 #include "modarith.hpp"
 
@@ -15,7 +18,9 @@ namespace ckks {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kChunk = 6;  // destination limbs per workgroup (grid.z splits the rest)
 
+template <int NS>
 __global__ void __launch_bounds__(kThreads)
     bconv_kernel(BConvArgs a, const PrimeDev* __restrict__ primes, int log_n) {
   const int item = blockIdx.y;
@@ -25,35 +30,56 @@ __global__ void __launch_bounds__(kThreads)
   const int shift = a.dst_shift[item];
   const size_t n = (size_t)1 << log_n;
   const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
-  const int ns = plan->ns, nd = plan->nd;
+  const int m0 = blockIdx.z * kChunk;
+  const int m1 = min(plan->nd, m0 + kChunk);
 
-  uint64_t y[kMaxSrc];
+  uint64_t y[NS];
 #pragma unroll
-  for (int j = 0; j < kMaxSrc; ++j) {
-    if (j < ns) {
-      const PrimeDev& ps = primes[plan->src[j]];
-      y[j] = shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], ps.q);
-    }
-  }
-  for (int m = 0; m < nd; ++m) {
+  for (int j = 0; j < NS; ++j)
+    y[j] = shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], primes[plan->src[j]].q);
+  for (int m = m0; m < m1; ++m) {
     const int di = plan->dst[m];
     const uint64_t q = primes[di].q, qn = primes[di].qinv_neg;
-    U128 acc = {0, 0};
+    const uint64_t* __restrict__ c = plan->hmod[m];
+    U128 acc = mul_wide(y[0], c[0]);
 #pragma unroll
-    for (int j = 0; j < kMaxSrc; ++j)
-      if (j < ns) add128(acc, mul_wide(y[j], plan->hmod[m][j]));
+    for (int j = 1; j < NS; ++j) add128(acc, mul_wide(y[j], c[j]));
     dst[(size_t)(di - shift) * n + p] = redc(acc, q, qn);
   }
 }
 
+template <int NS>
+hipError_t launch_ns(const ckks_params* P, const BConvArgs& a, int items, hipStream_t s) {
+  dim3 grid(P->n / kThreads, items, (a.max_nd + kChunk - 1) / kChunk);
+  hipLaunchKernelGGL((bconv_kernel<NS>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_bconv(const ckks_params* P, const BConvArgs& a, int items, hipStream_t s) {
+// All items of one launch have the same number of source limbs `ns`.
+hipError_t launch_bconv(const ckks_params* P, const BConvArgs& a, int items, int ns, hipStream_t s) {
   if (items <= 0) return hipSuccess;
-  dim3 grid(P->n / kThreads, items);
   ProfScope prof(CKKS_KERNEL_BCONV, s, (double)a.limbs_moved * P->n * 8);
-  hipLaunchKernelGGL(bconv_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
-  return hipGetLastError();
+  switch (ns) {
+    case 1: return launch_ns<1>(P, a, items, s);
+    case 2: return launch_ns<2>(P, a, items, s);
+    case 3: return launch_ns<3>(P, a, items, s);
+    case 4: return launch_ns<4>(P, a, items, s);
+    case 5: return launch_ns<5>(P, a, items, s);
+    case 6: return launch_ns<6>(P, a, items, s);
+    case 7: return launch_ns<7>(P, a, items, s);
+    case 8: return launch_ns<8>(P, a, items, s);
+    case 9: return launch_ns<9>(P, a, items, s);
+    case 10: return launch_ns<10>(P, a, items, s);
+    case 11: return launch_ns<11>(P, a, items, s);
+    case 12: return launch_ns<12>(P, a, items, s);
+    case 13: return launch_ns<13>(P, a, items, s);
+    case 14: return launch_ns<14>(P, a, items, s);
+    case 15: return launch_ns<15>(P, a, items, s);
+    case 16: return launch_ns<16>(P, a, items, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ckks

@@ -12,7 +12,8 @@ namespace ckks {
 
 constexpr int kMaxSrc = 16;    // basis-conversion source limbs
 constexpr int kMaxDst = 64;    // basis-conversion destination limbs (alpha + L + 1)
-constexpr int kMaxBeta = 8;    // key-switching digits
+constexpr int kMaxBeta = 4;    // key-switching digits
+constexpr int kMaxDig = 8;     // digit sets sharing one key read (hoisting)
 constexpr int kMaxKs = 8;      // keys applied to one digit set per launch
 constexpr int kMaxMacM = 16;   // plaintext-MAC inputs per launch
 constexpr int kMaxMacK = 8;    // plaintext-MAC accumulators per launch
@@ -24,8 +25,15 @@ struct PrimeDev {
   uint64_t r_lo, r_hi;     // floor(2^128 / q) (Barrett)
   uint64_t ninv, ninv_sh;  // N^-1 mod q and its Shoup companion
   uint64_t pmod, pmod_sh;  // P mod q (0 on the special primes) and companion
-  const uint64_t* tw;      // [4][N]: psi^br(i), Shoup, psi^-br(i), Shoup
+  const uint64_t* tw;      // [4][N]: psi^br(i), Shoup, psi^-br(i), Shoup (integer primes) or
+                           // the same powers as doubles and each divided by q (fp primes)
+  int fp;                  // q < 2^46: NTT butterflies in exact FP64 arithmetic
+  int pad;
+  double qd, qinv_d;       // q and 1/q as doubles
+  double ninv_d, ninv_q;   // N^-1 mod q as a double and divided by q
 };
+
+constexpr uint64_t kFpPrimeLimit = 1ull << 46;
 
 // Basis conversion eq. (3) from `ns` source limbs to `nd` destination limbs,
 // plus the final factor S^-1 of a division step (eq. (4), eq. (1)).
@@ -48,11 +56,12 @@ struct LimbRange {
   const uint64_t* aux;  // epilogue operand laid out like out (or null)
   int prime0;
   int count;
+  uint64_t* copy;       // inverse transforms: also store the input limbs here (or null)
   int epi0;             // plan index of the first limb's epilogue constant
   int pad;
 };
 
-constexpr int kMaxRanges = 8;
+constexpr int kMaxRanges = 16;
 struct NttArgs {
   int nr = 0;
   LimbRange r[kMaxRanges];
@@ -69,19 +78,33 @@ struct BConvArgs {
   uint64_t* dst[kMaxConv];        // destination limb m at dst + (plan.dst[m] - dst_shift) N
   int dst_shift[kMaxConv];
   int limbs_moved;                // sum over items of ns + nd (timing only)
+  int max_nd;                     // largest nd over the items
 };
 
+// Key-switch inner products of ndig digit sets with nkeys keys: output
+// (i, k) is phi_k(add_i + <d_i, key_k>), phi_k(<d_i, key_k>) (null = skipped).
 struct KsArgs {
-  const uint64_t* digits;  // [beta][K][N]
-  int beta, K, kmax;       // kmax: limb stride of the keys [beta_max][2][kmax][N]
-  int nkeys;
-  int add_pscaled;         // add is a Q-basis polynomial to be multiplied by P
-  int accumulate;          // out[dst] += value
+  int ndig, beta, K, kmax, nkeys, accumulate;
+  const uint64_t* digits[kMaxDig];  // [beta][K][N] each
+  const uint64_t* add[kMaxDig];     // [K][N], or Q-basis [K - alpha][N] to be multiplied by P, or null
+  int add_pscaled[kMaxDig];
+  const uint64_t* key[kMaxKs];      // [beta_max][2][kmax][N]
+  uint32_t gal_inv[kMaxKs];         // Galois element of -r: value at p is stored at auto_index(p, gal_inv)
+  uint64_t* out_a[kMaxDig][kMaxKs];
+  uint64_t* out_b[kMaxDig][kMaxKs];
+};
+
+// Outer layer of Algorithm 2 (lines 17-18) for all giant steps at once, as a
+// gather: c0[p] += sum_k (u0_k + <d_k, key_k,0>)[src_k(p)],
+//         c1[p] += sum_k <d_k, key_k,1>[src_k(p)], src_k = phi index of r_k.
+struct KsGatherArgs {
+  int nk, beta, K, kmax;
+  const uint64_t* digits[kMaxKs];  // [beta][K][N]
   const uint64_t* key[kMaxKs];
-  uint32_t gal_inv[kMaxKs];  // Galois element of -r: value at p is written to phi index of p
-  const uint64_t* add;       // [K][N] (or [K - alpha][N] if add_pscaled), may be null
-  uint64_t* out_a[kMaxKs];
-  uint64_t* out_b[kMaxKs];
+  const uint64_t* add[kMaxKs];     // u0_k [K][N]
+  uint32_t gal[kMaxKs];            // Galois element of r_k
+  uint64_t* c0;
+  uint64_t* c1;
 };
 
 struct MacArgs {
@@ -123,8 +146,9 @@ class ProfScope {
 // Kernel launchers.
 hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
                       const BConvPlan* epi_plan, hipStream_t s);
-hipError_t launch_bconv(const struct ::ckks_params* P, const BConvArgs& a, int items, hipStream_t s);
+hipError_t launch_bconv(const struct ::ckks_params* P, const BConvArgs& a, int items, int ns, hipStream_t s);
 hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipStream_t s);
+hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGatherArgs& a, hipStream_t s);
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
 hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
 

@@ -24,6 +24,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
+template <int NDIG>
 __global__ void __launch_bounds__(kThreads)
     ks_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
@@ -32,40 +33,91 @@ __global__ void __launch_bounds__(kThreads)
   const PrimeDev& pr = primes[l];
   const uint64_t q = pr.q;
 
-  uint64_t d[kMaxBeta];
+  uint64_t d[NDIG][kMaxBeta], addv[NDIG];
 #pragma unroll
-  for (int b = 0; b < kMaxBeta; ++b)
-    if (b < a.beta) d[b] = a.digits[((size_t)b * a.K + l) * n + p];
-
-  uint64_t addv = 0;
-  if (a.add) {
-    if (a.add_pscaled)
-      addv = (l < alpha) ? 0 : shoup(a.add[(size_t)(l - alpha) * n + p], pr.pmod, pr.pmod_sh, q);
-    else
-      addv = a.add[(size_t)l * n + p];
+  for (int i = 0; i < NDIG; ++i) {
+#pragma unroll
+    for (int b = 0; b < kMaxBeta; ++b)
+      if (b < a.beta) d[i][b] = a.digits[i][((size_t)b * a.K + l) * n + p];
+    addv[i] = 0;
+    if (a.add[i]) {
+      if (a.add_pscaled[i])
+        addv[i] = (l < alpha) ? 0 : shoup(a.add[i][(size_t)(l - alpha) * n + p], pr.pmod, pr.pmod_sh, q);
+      else
+        addv[i] = a.add[i][(size_t)l * n + p];
+    }
   }
-
   for (int k = 0; k < a.nkeys; ++k) {
     const uint64_t* __restrict__ key = a.key[k];
+    uint64_t k0[kMaxBeta], k1[kMaxBeta];
+#pragma unroll
+    for (int b = 0; b < kMaxBeta; ++b) {
+      if (b < a.beta) {
+        k0[b] = key[(((size_t)b * 2 + 0) * a.kmax + l) * n + p];
+        k1[b] = key[(((size_t)b * 2 + 1) * a.kmax + l) * n + p];
+      }
+    }
+    const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
+#pragma unroll
+    for (int i = 0; i < NDIG; ++i) {
+      uint64_t* oa = a.out_a[i][k];
+      if (!oa) continue;
+      uint64_t* ob = a.out_b[i][k];
+      U128 x = {0, 0}, y = {0, 0};
+#pragma unroll
+      for (int b = 0; b < kMaxBeta; ++b) {
+        if (b < a.beta) {
+          add128(x, mul_wide(d[i][b], k0[b]));
+          add128(y, mul_wide(d[i][b], k1[b]));
+        }
+      }
+      const uint64_t xr = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv[i], q);
+      const uint64_t yr = barrett128(y, q, pr.r_lo, pr.r_hi);
+      if (a.accumulate) {
+        oa[o] = add_mod(oa[o], xr, q);
+        ob[o] = add_mod(ob[o], yr, q);
+      } else {
+        oa[o] = xr;
+        ob[o] = yr;
+      }
+    }
+  }
+}
+
+template <int NDIG>
+hipError_t launch_ks(const ckks_params* P, const KsArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  hipLaunchKernelGGL((ks_kernel<NDIG>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kThreads)
+    ks_gather_kernel(KsGatherArgs a, const PrimeDev* __restrict__ primes, int log_n) {
+  const size_t n = (size_t)1 << log_n;
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const PrimeDev& pr = primes[l];
+  const uint64_t q = pr.q;
+  const size_t o = (size_t)l * n + p;
+  uint64_t c0 = a.c0[o], c1 = a.c1[o];
+  for (int k = 0; k < a.nk; ++k) {
+    const size_t s = (size_t)l * n + auto_index(p, a.gal[k], log_n);
+    const uint64_t* __restrict__ key = a.key[k];
+    const uint64_t* __restrict__ dg = a.digits[k];
     U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b) {
       if (b < a.beta) {
-        add128(x, mul_wide(d[b], key[(((size_t)b * 2 + 0) * a.kmax + l) * n + p]));
-        add128(y, mul_wide(d[b], key[(((size_t)b * 2 + 1) * a.kmax + l) * n + p]));
+        const uint64_t d = dg[(size_t)b * a.K * n + s];
+        add128(x, mul_wide(d, key[((size_t)b * 2 + 0) * a.kmax * n + s]));
+        add128(y, mul_wide(d, key[((size_t)b * 2 + 1) * a.kmax * n + s]));
       }
     }
-    const uint64_t xr = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
-    const uint64_t yr = barrett128(y, q, pr.r_lo, pr.r_hi);
-    const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
-    if (a.accumulate) {
-      a.out_a[k][o] = add_mod(a.out_a[k][o], xr, q);
-      a.out_b[k][o] = add_mod(a.out_b[k][o], yr, q);
-    } else {
-      a.out_a[k][o] = xr;
-      a.out_b[k][o] = yr;
-    }
+    c0 = add_mod(c0, add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), a.add[k][s], q), q);
+    c1 = add_mod(c1, barrett128(y, q, pr.r_lo, pr.r_hi), q);
   }
+  a.c0[o] = c0;
+  a.c1[o] = c1;
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -130,11 +182,31 @@ __global__ void __launch_bounds__(kThreads)
 }  // namespace
 
 hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s) {
-  dim3 grid(P->n / kThreads, a.K);
-  const double words = (double)a.K * P->n *
-                       (a.beta + a.nkeys * (2.0 * a.beta + 2 + (a.accumulate ? 2 : 0)) + (a.add ? 1 : 0));
+  double words = 0;
+  for (int i = 0; i < a.ndig; ++i) {
+    words += a.beta + (a.add[i] ? 1 : 0);
+    for (int k = 0; k < a.nkeys; ++k) words += a.out_a[i][k] ? (a.accumulate ? 4 : 2) : 0;
+  }
+  words += 2.0 * a.beta * a.nkeys;
+  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * a.K * P->n * 8);
+  switch (a.ndig) {
+    case 1: return launch_ks<1>(P, a, s);
+    case 2: return launch_ks<2>(P, a, s);
+    case 3: return launch_ks<3>(P, a, s);
+    case 4: return launch_ks<4>(P, a, s);
+    case 5: return launch_ks<5>(P, a, s);
+    case 6: return launch_ks<6>(P, a, s);
+    case 7: return launch_ks<7>(P, a, s);
+    case 8: return launch_ks<8>(P, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_keyswitch_gather(const ckks_params* P, const KsGatherArgs& a, hipStream_t s) {
+  const double words = (double)a.K * P->n * (4.0 + a.nk * (3.0 * a.beta + 1));
   ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * 8);
-  hipLaunchKernelGGL(ks_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  dim3 grid(P->n / kThreads, a.K);
+  hipLaunchKernelGGL(ks_gather_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
   return hipGetLastError();
 }
 

@@ -34,156 +34,228 @@ struct Run {
 
 // ---- primitive steps ------------------------------------------------------
 
+LimbRange range(const uint64_t* in, uint64_t* out, int prime0, int count, const uint64_t* aux = nullptr,
+                uint64_t* copy = nullptr) {
+  LimbRange r;
+  r.in = in;
+  r.out = out;
+  r.aux = aux;
+  r.prime0 = prime0;
+  r.count = count;
+  r.copy = copy;
+  r.epi0 = 0;
+  r.pad = 0;
+  return r;
+}
+
 void ntt_range(Run& R, bool fwd, int prime0, int count, const uint64_t* in, uint64_t* out) {
   if (R.dry || R.err || count <= 0) return;
   NttArgs a;
   a.nr = 1;
-  a.r[0] = LimbRange{in, out, nullptr, prime0, count, 0, 0};
+  a.r[0] = range(in, out, prime0, count);
   R.check(launch_ntt(R.P, fwd, a, count, EPI_NONE, nullptr, R.s));
 }
 
-void copy_limbs(Run& R, uint64_t* dst, const uint64_t* src, size_t count) {
-  if (R.dry || R.err || count == 0) return;
-  R.check(hipMemcpyAsync(dst, src, count * R.N * 8, hipMemcpyDeviceToDevice, R.s));
-}
+// Collects limb ranges into NTT launches (flushing when the table is full).
+struct NttBatch {
+  Run& R;
+  bool fwd;
+  int epi;
+  const BConvPlan* plan;
+  NttArgs a;
+  int total = 0;
+  NttBatch(Run& r, bool f, int e = EPI_NONE, const BConvPlan* pl = nullptr) : R(r), fwd(f), epi(e), plan(pl) {
+    a.nr = 0;
+  }
+  void add(const LimbRange& r) {
+    if (r.count <= 0) return;
+    if (a.nr == kMaxRanges) flush();
+    a.r[a.nr++] = r;
+    total += r.count;
+  }
+  void flush() {
+    if (a.nr && !R.dry && !R.err) R.check(launch_ntt(R.P, fwd, a, total, epi, plan, R.s));
+    a.nr = 0;
+    total = 0;
+  }
+  ~NttBatch() { flush(); }
+};
 
-// Decompose (Fig. 1): x (level l, Q basis, NTT) -> digits [beta][K][N].
-void decompose(Run& R, int level, const uint64_t* x, uint64_t* digits) {
+// Collects basis conversions with the same number of source limbs.
+struct BConvBatch {
+  Run& R;
+  int ns;
+  BConvArgs a;
+  int items = 0;
+  BConvBatch(Run& r, int n) : R(r), ns(n) { reset(); }
+  void reset() {
+    memset(&a, 0, sizeof(a));
+    items = 0;
+  }
+  void add(const BConvPlan* plan, int nd, const uint64_t* src, uint64_t* dst, int shift) {
+    if (items == kMaxConv) flush();
+    a.plan[items] = plan;
+    a.src[items] = src;
+    a.dst[items] = dst;
+    a.dst_shift[items] = shift;
+    a.limbs_moved += ns + nd;
+    a.max_nd = std::max(a.max_nd, nd);
+    ++items;
+  }
+  void flush() {
+    if (items && !R.dry && !R.err) R.check(launch_bconv(R.P, a, items, ns, R.s));
+    reset();
+  }
+  ~BConvBatch() { flush(); }
+};
+
+typedef std::vector<std::pair<const uint64_t*, uint64_t*>> IOList;
+
+// Decompose (Fig. 1) of several level-l Q-basis polynomials (NTT form) into
+// digits [beta][K][N] each.  The inverse NTT's first pass also stores each
+// group's own limbs, unchanged, into its digit (ModUp keeps them, R15).
+void decompose(Run& R, int level, const IOList& xs) {
   const ckks_params* P = R.P;
   const int a = P->alpha, K = P->K(level), beta = P->beta(level), Lq = level + 1;
   const size_t N = R.N, mark = R.ws.mark();
-  uint64_t* coef = R.limbs(Lq);
-  ntt_range(R, false, a, Lq, x, coef);
+  std::vector<uint64_t*> coef(xs.size());
+  for (size_t t = 0; t < xs.size(); ++t) coef[t] = R.limbs(Lq);
   if (!R.dry && !R.err) {
-    for (int b0 = 0; b0 < beta; b0 += kMaxConv) {
-      BConvArgs ba;
-      int items = 0;
-      for (int b = b0; b < std::min(beta, b0 + kMaxConv); ++b, ++items) {
-        ba.plan[items] = P->plan(P->plan_decomp[(size_t)level * P->beta_max + b]);
-        ba.src[items] = coef + (size_t)a * b * N;
-        ba.dst[items] = digits + (size_t)b * K * N;
-        ba.dst_shift[items] = 0;
+    {
+      NttBatch inv(R, false);
+      for (size_t t = 0; t < xs.size(); ++t)
+        for (int b = 0; b < beta; ++b) {
+          const int lo = b * a, hi = std::min(lo + a - 1, level);
+          inv.add(range(xs[t].first + (size_t)lo * N, coef[t] + (size_t)lo * N, a + lo, hi - lo + 1, nullptr,
+                        xs[t].second + ((size_t)b * K + a + lo) * N));
+        }
+    }
+    // Digits with a full group of alpha limbs share launches; a shorter last
+    // group has its own.
+    const int last = level - (beta - 1) * a + 1;
+    {
+      BConvBatch full(R, a);
+      BConvBatch part(R, last);
+      for (size_t t = 0; t < xs.size(); ++t)
+        for (int b = 0; b < beta; ++b) {
+          const int lo = b * a, hi = std::min(lo + a - 1, level), g = hi - lo + 1;
+          const BConvPlan* pl = P->plan(P->plan_decomp[(size_t)level * P->beta_max + b]);
+          (g == a ? full : part).add(pl, K - g, coef[t] + (size_t)lo * N, xs[t].second + (size_t)b * K * N, 0);
+        }
+    }
+    NttBatch fwd(R, true);
+    for (size_t t = 0; t < xs.size(); ++t)
+      for (int b = 0; b < beta; ++b) {
+        const int lo = b * a, hi = std::min(lo + a - 1, level);
+        uint64_t* d = xs[t].second + (size_t)b * K * N;
+        fwd.add(range(d, d, 0, a + lo));
+        fwd.add(range(d + (size_t)(a + hi + 1) * N, d + (size_t)(a + hi + 1) * N, a + hi + 1, K - (a + hi + 1)));
       }
-      ba.limbs_moved = 0;
-      for (int i = 0; i < items; ++i) {
-        const int lo = (b0 + i) * a, hi = std::min(lo + a - 1, level);
-        ba.limbs_moved += K;  // group limbs read, every other PQ limb written
-        (void)hi;
-      }
-      R.check(launch_bconv(P, ba, items, R.s));
-    }
-    NttArgs na;
-    int total = 0;
-    auto flush = [&]() {
-      if (na.nr) R.check(launch_ntt(P, true, na, total, EPI_NONE, nullptr, R.s));
-      na.nr = 0;
-      total = 0;
-    };
-    auto add = [&](uint64_t* p, int prime0, int count) {
-      if (count <= 0) return;
-      if (na.nr == kMaxRanges) flush();
-      na.r[na.nr++] = LimbRange{p, p, nullptr, prime0, count, 0, 0};
-      total += count;
-    };
-    for (int b = 0; b < beta; ++b) {
-      const int lo = b * a, hi = std::min(lo + a - 1, level);
-      uint64_t* d = digits + (size_t)b * K * N;
-      add(d, 0, a + lo);
-      add(d + (size_t)(a + hi + 1) * N, a + hi + 1, K - (a + hi + 1));
-    }
-    flush();
-    for (int b = 0; b < beta; ++b) {
-      const int lo = b * a, hi = std::min(lo + a - 1, level);
-      copy_limbs(R, digits + ((size_t)b * K + a + lo) * N, x + (size_t)lo * N, hi - lo + 1);
-    }
   }
   R.ws.reset(mark);
 }
 
+void decompose(Run& R, int level, const uint64_t* x, uint64_t* digits) { decompose(R, level, IOList{{x, digits}}); }
+
 enum DivKind { DIV_MODDOWN, DIV_MODDOWN_RESCALE, DIV_RESCALE };
 
-// Division step of eq. (4) / eq. (1):
+// Division step of eq. (4) / eq. (1), for several inputs of the same kind:
 //  DIV_MODDOWN:         x [alpha+l+1] -> out [l+1], divide by P
 //  DIV_MODDOWN_RESCALE: x [alpha+l+1] -> out [l],   divide by P q_l
 //  DIV_RESCALE:         x [l+1]       -> out [l],   divide by q_l
-void divide(Run& R, DivKind kind, int level, const uint64_t* x, uint64_t* out) {
+void divide(Run& R, DivKind kind, int level, const IOList& xs) {
   const ckks_params* P = R.P;
   const int a = P->alpha;
   const size_t N = R.N, mark = R.ws.mark();
   int plan_idx, ns, nout;
-  const uint64_t* keep;  // limbs that survive, aligned with out
   if (kind == DIV_MODDOWN) {
     plan_idx = P->plan_moddown[level];
     ns = a;
     nout = level + 1;
-    keep = x + (size_t)a * N;
   } else if (kind == DIV_MODDOWN_RESCALE) {
     plan_idx = P->plan_mdrescale[level];
     ns = a + 1;
     nout = level;
-    keep = x + (size_t)a * N;
   } else {
     plan_idx = P->plan_rescale[level];
     ns = 1;
     nout = level;
-    keep = x;
   }
-  uint64_t* coef = R.limbs(ns);
+  std::vector<uint64_t*> coef(xs.size());
+  for (size_t t = 0; t < xs.size(); ++t) coef[t] = R.limbs(ns);
   if (!R.dry && !R.err) {
     const BConvPlan* plan = P->plan(plan_idx);
-    NttArgs na;
-    if (kind == DIV_RESCALE) {
-      na.nr = 1;
-      na.r[0] = LimbRange{x + (size_t)level * N, coef, nullptr, a + level, 1, 0, 0};
-    } else {
-      na.nr = 1;
-      na.r[0] = LimbRange{x, coef, nullptr, 0, a, 0, 0};
-      if (kind == DIV_MODDOWN_RESCALE) {
-        na.nr = 2;
-        na.r[1] = LimbRange{x + (size_t)(a + level) * N, coef + (size_t)a * N, nullptr, a + level, 1, 0, 0};
+    {
+      NttBatch inv(R, false);
+      for (size_t t = 0; t < xs.size(); ++t) {
+        const uint64_t* x = xs[t].first;
+        if (kind == DIV_RESCALE) {
+          inv.add(range(x + (size_t)level * N, coef[t], a + level, 1));
+        } else {
+          inv.add(range(x, coef[t], 0, a));
+          if (kind == DIV_MODDOWN_RESCALE)
+            inv.add(range(x + (size_t)(a + level) * N, coef[t] + (size_t)a * N, a + level, 1));
+        }
       }
     }
-    R.check(launch_ntt(P, false, na, ns, EPI_NONE, nullptr, R.s));
-    BConvArgs ba;
-    ba.plan[0] = plan;
-    ba.src[0] = coef;
-    ba.dst[0] = out;
-    ba.dst_shift[0] = a;
-    ba.limbs_moved = ns + nout;
-    R.check(launch_bconv(P, ba, 1, R.s));
-    NttArgs nf;
-    nf.nr = 1;
-    nf.r[0] = LimbRange{out, out, keep, a, nout, 0, 0};
-    R.check(launch_ntt(P, true, nf, nout, EPI_SUBMUL, plan, R.s));
+    {
+      BConvBatch bc(R, ns);
+      for (size_t t = 0; t < xs.size(); ++t) bc.add(plan, nout, coef[t], xs[t].second, a);
+    }
+    NttBatch fwd(R, true, EPI_SUBMUL, plan);
+    for (size_t t = 0; t < xs.size(); ++t) {
+      const uint64_t* keep = kind == DIV_RESCALE ? xs[t].first : xs[t].first + (size_t)a * N;
+      fwd.add(range(xs[t].second, xs[t].second, a, nout, keep));
+    }
   }
   R.ws.reset(mark);
 }
 
-// Key-switch inner products of one digit set with several keys, phi on write.
-void keyswitch(Run& R, int level, const uint64_t* digits, const std::vector<const uint64_t*>& keys,
-               const std::vector<uint32_t>& gal_inv, const uint64_t* add, bool add_pscaled, bool accumulate,
-               const std::vector<uint64_t*>& out_a, const std::vector<uint64_t*>& out_b) {
-  if (R.dry || R.err) return;
+void divide(Run& R, DivKind kind, int level, const uint64_t* x, uint64_t* out) {
+  divide(R, kind, level, IOList{{x, out}});
+}
+
+// Key-switch inner products of several digit sets with several keys, phi on
+// write (hoisting: each digit set and each key is read once per launch).
+struct KsDigit {
+  const uint64_t* digits;
+  const uint64_t* add;   // may be null
+  bool add_pscaled;
+};
+struct KsKey {
+  const uint64_t* key;
+  uint32_t gal_inv;
+};
+// out[i][k] = {a, b} destination of digit set i with key k (nulls skip).
+void keyswitch(Run& R, int level, const std::vector<KsDigit>& dig, const std::vector<KsKey>& keys,
+               const std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>>& out, bool accumulate) {
+  if (R.dry || R.err || dig.empty() || keys.empty()) return;
   const ckks_params* P = R.P;
-  for (size_t k0 = 0; k0 < keys.size(); k0 += kMaxKs) {
-    KsArgs ka;
-    memset(&ka, 0, sizeof(ka));
-    ka.digits = digits;
-    ka.beta = P->beta(level);
-    ka.K = P->K(level);
-    ka.kmax = P->Kmax();
-    ka.add = add;
-    ka.add_pscaled = add_pscaled ? 1 : 0;
-    ka.accumulate = accumulate ? 1 : 0;
-    int nk = 0;
-    for (size_t k = k0; k < std::min(keys.size(), k0 + kMaxKs); ++k, ++nk) {
-      ka.key[nk] = keys[k];
-      ka.gal_inv[nk] = gal_inv[k];
-      ka.out_a[nk] = out_a[k];
-      ka.out_b[nk] = out_b[k];
+  for (size_t i0 = 0; i0 < dig.size(); i0 += kMaxDig) {
+    for (size_t k0 = 0; k0 < keys.size(); k0 += kMaxKs) {
+      KsArgs ka;
+      memset(&ka, 0, sizeof(ka));
+      ka.beta = P->beta(level);
+      ka.K = P->K(level);
+      ka.kmax = P->Kmax();
+      ka.accumulate = accumulate ? 1 : 0;
+      ka.ndig = (int)std::min(dig.size() - i0, (size_t)kMaxDig);
+      ka.nkeys = (int)std::min(keys.size() - k0, (size_t)kMaxKs);
+      for (int i = 0; i < ka.ndig; ++i) {
+        ka.digits[i] = dig[i0 + i].digits;
+        ka.add[i] = dig[i0 + i].add;
+        ka.add_pscaled[i] = dig[i0 + i].add_pscaled ? 1 : 0;
+        for (int k = 0; k < ka.nkeys; ++k) {
+          ka.out_a[i][k] = out[i0 + i][k0 + k].first;
+          ka.out_b[i][k] = out[i0 + i][k0 + k].second;
+        }
+      }
+      for (int k = 0; k < ka.nkeys; ++k) {
+        ka.key[k] = keys[k0 + k].key;
+        ka.gal_inv[k] = keys[k0 + k].gal_inv;
+      }
+      R.check(launch_keyswitch(P, ka, R.s));
     }
-    ka.nkeys = nk;
-    R.check(launch_keyswitch(P, ka, R.s));
   }
 }
 
@@ -256,26 +328,57 @@ struct KeySet {
   }
 };
 
-// Rot(ct, r) = (phi_r(c0 + x), phi_r(y)), (x, y) = ModDown(<Decompose(c1), swk~_r>).
-void rotate(Run& R, int level, const uint64_t* c0, const uint64_t* c1, long r, const KeySet& ks, uint64_t* o0,
-            uint64_t* o1, bool accumulate) {
+// Rot(ct, r) = (phi_r(c0 + x), phi_r(y)), (x, y) = ModDown(<Decompose(c1), swk~_r>),
+// for several independent rotations at once (each with its own Decompose, as
+// plain BSGS and the diagonal method prescribe; only the launches are shared).
+struct RotJob {
+  const uint64_t* c0;
+  const uint64_t* c1;
+  long r;
+  uint64_t* o0;
+  uint64_t* o1;
+  bool accumulate;  // o += Rot(ct, r)
+};
+
+void rotate(Run& R, int level, const std::vector<RotJob>& jobs, const KeySet& ks) {
   const ckks_params* P = R.P;
-  const int K = P->K(level), Lq = level + 1;
-  const uint64_t* key = ks.get(R, r);
-  const size_t mark = R.ws.mark();
-  uint64_t* D = R.limbs((size_t)P->beta(level) * K);
-  uint64_t* X = R.limbs(K);
-  uint64_t* Y = R.limbs(K);
-  uint64_t* Xq = R.limbs(Lq);
-  uint64_t* Yq = R.limbs(Lq);
-  decompose(R, level, c1, D);
-  keyswitch(R, level, D, {key}, {1u}, nullptr, false, false, {X}, {Y});
-  divide(R, DIV_MODDOWN, level, X, Xq);
-  divide(R, DIV_MODDOWN, level, Y, Yq);
-  const uint32_t g = galois(P, r);
-  automorph(R, Lq, P->alpha, g, Xq, c0, o0, accumulate);
-  automorph(R, Lq, P->alpha, g, Yq, nullptr, o1, accumulate);
-  R.ws.reset(mark);
+  const int K = P->K(level), Lq = level + 1, beta = P->beta(level);
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxDig) {
+    const size_t nj = std::min(jobs.size() - j0, (size_t)kMaxDig);
+    const size_t mark = R.ws.mark();
+    std::vector<uint64_t*> D(nj), X(nj), Y(nj), Xq(nj), Yq(nj);
+    IOList dc, md;
+    std::vector<KsDigit> dig;
+    std::vector<KsKey> keys;
+    std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>> out(nj);
+    for (size_t t = 0; t < nj; ++t) {
+      D[t] = R.limbs((size_t)beta * K);
+      X[t] = R.limbs(K);
+      Y[t] = R.limbs(K);
+      Xq[t] = R.limbs(Lq);
+      Yq[t] = R.limbs(Lq);
+    }
+    for (size_t t = 0; t < nj; ++t) {
+      const RotJob& J = jobs[j0 + t];
+      dc.push_back({J.c1, D[t]});
+      md.push_back({X[t], Xq[t]});
+      md.push_back({Y[t], Yq[t]});
+      dig.push_back(KsDigit{D[t], nullptr, false});
+      keys.push_back(KsKey{ks.get(R, J.r), 1u});
+      for (size_t u = 0; u < nj; ++u)
+        out[t].push_back(u == t ? std::make_pair(X[t], Y[t]) : std::make_pair((uint64_t*)nullptr, (uint64_t*)nullptr));
+    }
+    decompose(R, level, dc);
+    keyswitch(R, level, dig, keys, out, false);
+    divide(R, DIV_MODDOWN, level, md);
+    for (size_t t = 0; t < nj; ++t) {
+      const RotJob& J = jobs[j0 + t];
+      const uint32_t g = galois(P, J.r);
+      automorph(R, Lq, P->alpha, g, Xq[t], J.c0, J.o0, J.accumulate);
+      automorph(R, Lq, P->alpha, g, Yq[t], nullptr, J.o1, J.accumulate);
+    }
+    R.ws.reset(mark);
+  }
 }
 
 struct Diag {
@@ -315,46 +418,67 @@ void lt_th(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, in
     U0[k] = R.limbs(K);
     U1[k] = R.limbs(K);
   }
-  uint64_t* tmpQ = R.limbs(Lq);
-  uint64_t* Dout = R.limbs((size_t)beta * K);
+  std::vector<uint64_t*> tmpQ(n1, nullptr), tmpK(n3, nullptr), Dk(n3, nullptr);
+  for (int i = 1; i < n1; ++i)
+    if (mid_i[i]) tmpQ[i] = R.limbs(Lq);
+  for (int k = 1; k < n3; ++k)
+    if (used_k[k]) {
+      tmpK[k] = R.limbs(Lq);
+      Dk[k] = R.limbs((size_t)beta * K);
+    }
 
   // Line 1: d_0 = Decompose(c1').
   if (need_d0) decompose(R, level, c1, Dg[0]);
   // Lines 3-5: inner rotations share d_0; a_0 = P c0' is applied inside the kernel.
   {
-    std::vector<const uint64_t*> keys;
-    std::vector<uint32_t> gi;
-    std::vector<uint64_t*> oa, ob;
+    std::vector<KsKey> keys;
+    std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>> out(1);
     for (int i = 1; i < n1; ++i) {
       if (!used_i[i]) continue;
-      keys.push_back(ks.get(R, i));
-      gi.push_back(galois(P, -i));
-      oa.push_back(A[i]);
-      ob.push_back(B[i]);
+      keys.push_back(KsKey{ks.get(R, i), galois(P, -i)});
+      out[0].push_back({A[i], B[i]});
     }
-    if (!keys.empty()) keyswitch(R, level, Dg[0], keys, gi, c0, true, false, oa, ob);
+    keyswitch(R, level, {KsDigit{Dg[0], c0, true}}, keys, out, false);
   }
-  // Lines 6-7: d_i = Decompose(ModDown(b_i)).
-  for (int i = 1; i < n1; ++i) {
-    if (!mid_i[i]) continue;
-    divide(R, DIV_MODDOWN, level, B[i], tmpQ);
-    decompose(R, level, tmpQ, Dg[i]);
+  // Lines 6-7: d_i = Decompose(ModDown(b_i)), all i at once (independent).
+  {
+    IOList md, dc;
+    for (int i = 1; i < n1; ++i) {
+      if (!mid_i[i]) continue;
+      md.push_back({B[i], tmpQ[i]});
+      dc.push_back({tmpQ[i], Dg[i]});
+    }
+    if (!md.empty()) {
+      divide(R, DIV_MODDOWN, level, md);
+      decompose(R, level, dc);
+    }
   }
-  // Lines 8-11: middle rotations by n1 j share d_i.
-  for (int i = 0; i < n1; ++i) {
-    if (!mid_i[i]) continue;
-    std::vector<const uint64_t*> keys;
-    std::vector<uint32_t> gi;
-    std::vector<uint64_t*> oa, ob;
+  // Lines 8-11: middle rotations by n1 j share d_i; one launch reads every
+  // middle key once for all digit sets d_0 .. d_{n1-1}.
+  {
+    std::vector<KsDigit> dig;
+    std::vector<int> di;
+    for (int i = 0; i < n1; ++i)
+      if (mid_i[i]) {
+        dig.push_back(KsDigit{Dg[i], i == 0 ? c0 : A[i], i == 0});
+        di.push_back(i);
+      }
+    std::vector<KsKey> keys;
+    std::vector<int> kj;
     for (int j = 1; j < n2; ++j) {
-      const int m = n1 * j + i;
-      if (!used_m[m]) continue;
-      keys.push_back(ks.get(R, (long)n1 * j));
-      gi.push_back(galois(P, -(long)n1 * j));
-      oa.push_back(A[m]);
-      ob.push_back(B[m]);
+      bool any = false;
+      for (int i : di) any = any || used_m[n1 * j + i];
+      if (!any) continue;
+      keys.push_back(KsKey{ks.get(R, (long)n1 * j), galois(P, -(long)n1 * j)});
+      kj.push_back(j);
     }
-    if (!keys.empty()) keyswitch(R, level, Dg[i], keys, gi, i == 0 ? c0 : A[i], i == 0, false, oa, ob);
+    std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>> out(dig.size());
+    for (size_t x = 0; x < dig.size(); ++x)
+      for (int j : kj) {
+        const int m = n1 * j + di[x];
+        out[x].push_back(used_m[m] ? std::make_pair(A[m], B[m]) : std::make_pair((uint64_t*)nullptr, (uint64_t*)nullptr));
+      }
+    keyswitch(R, level, dig, keys, out, false);
   }
   // Lines 12 and 14: all plaintext products at once.
   {
@@ -383,17 +507,43 @@ void lt_th(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, in
     }
     ptmac(R, K, 0, terms, oo0, oo1);
   }
-  // Lines 13-18: outer rotations by n1 n2 k.
-  for (int k = 1; k < n3; ++k) {
-    if (!used_k[k]) continue;
-    divide(R, DIV_MODDOWN, level, U1[k], tmpQ);
-    decompose(R, level, tmpQ, Dout);
-    const long G = (long)inner * k;
-    keyswitch(R, level, Dout, {ks.get(R, G)}, {galois(P, -G)}, U0[k], false, true, {U0[0]}, {U1[0]});
+  // Lines 13-18: outer rotations by n1 n2 k, all k at once: ModDown and
+  // Decompose batched, then one gather kernel adds phi_G(u0 + x), phi_G(y)
+  // of every k into (c0, c1).
+  {
+    IOList md, dc;
+    std::vector<int> kk;
+    for (int k = 1; k < n3; ++k) {
+      if (!used_k[k]) continue;
+      md.push_back({U1[k], tmpK[k]});
+      dc.push_back({tmpK[k], Dk[k]});
+      kk.push_back(k);
+    }
+    if (!kk.empty()) {
+      divide(R, DIV_MODDOWN, level, md);
+      decompose(R, level, dc);
+      for (size_t k0 = 0; k0 < kk.size(); k0 += kMaxKs) {
+        KsGatherArgs ga;
+        memset(&ga, 0, sizeof(ga));
+        ga.beta = beta;
+        ga.K = K;
+        ga.kmax = P->Kmax();
+        ga.c0 = U0[0];
+        ga.c1 = U1[0];
+        for (size_t t = k0; t < std::min(kk.size(), k0 + kMaxKs); ++t) {
+          const long G = (long)inner * kk[t];
+          ga.digits[ga.nk] = Dk[kk[t]];
+          ga.key[ga.nk] = ks.get(R, G);
+          ga.add[ga.nk] = U0[kk[t]];
+          ga.gal[ga.nk] = galois(P, G);
+          ++ga.nk;
+        }
+        if (!R.dry && !R.err) R.check(launch_keyswitch_gather(P, ga, R.s));
+      }
+    }
   }
   // Line 19: ModDown by P q_l (ModDown and rescale combined).
-  divide(R, DIV_MODDOWN_RESCALE, level, U0[0], o0);
-  divide(R, DIV_MODDOWN_RESCALE, level, U1[0], o1);
+  divide(R, DIV_MODDOWN_RESCALE, level, IOList{{U0[0], o0}, {U1[0], o1}});
   (void)N;
 }
 
@@ -406,7 +556,7 @@ void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
   for (int j = 0; j < n2; ++j)
     for (int i = 0; i < n1; ++i)
       if (D.has(n1 * j + i)) used_i[i] = 1, used_j[j] = 1;
-  std::vector<uint64_t*> R0(n1, nullptr), R1(n1, nullptr);
+  std::vector<uint64_t*> R0(n1, nullptr), R1(n1, nullptr), S0(n2, nullptr), S1(n2, nullptr);
   R0[0] = const_cast<uint64_t*>(c0);
   R1[0] = const_cast<uint64_t*>(c1);
   for (int i = 1; i < n1; ++i)
@@ -416,30 +566,47 @@ void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
     }
   uint64_t* A0 = R.limbs(Lq);
   uint64_t* A1 = R.limbs(Lq);
-  uint64_t* S0 = R.limbs(Lq);
-  uint64_t* S1 = R.limbs(Lq);
-  for (int i = 1; i < n1; ++i)
-    if (used_i[i]) rotate(R, level, c0, c1, i, ks, R0[i], R1[i], false);
-  bool acc_init = false;
-  for (int j = 0; j < n2; ++j) {
-    if (!used_j[j]) continue;
-    std::vector<MacTerm> terms;
-    for (int i = 0; i < n1; ++i) {
-      if (!D.has(n1 * j + i)) continue;
-      terms.push_back(MacTerm{R0[i], R1[i], false, {D.pt[n1 * j + i]}});
+  for (int j = 1; j < n2; ++j)
+    if (used_j[j]) {
+      S0[j] = R.limbs(Lq);
+      S1[j] = R.limbs(Lq);
     }
-    if (j == 0) {
-      ptmac(R, Lq, P->alpha, terms, {A0}, {A1});
-      acc_init = true;
-    } else {
-      ptmac(R, Lq, P->alpha, terms, {S0}, {S1});
-      rotate(R, level, S0, S1, (long)n1 * j, ks, A0, A1, acc_init);
-      acc_init = true;
-    }
+  // Baby steps: ct_i = Rot(ct, i), each with its own Decompose.
+  {
+    std::vector<RotJob> jobs;
+    for (int i = 1; i < n1; ++i)
+      if (used_i[i]) jobs.push_back(RotJob{c0, c1, (long)i, R0[i], R1[i], false});
+    rotate(R, level, jobs, ks);
   }
-  if (!acc_init) ptmac(R, Lq, P->alpha, {MacTerm{c0, c1, false, {nullptr}}}, {A0}, {A1});
-  divide(R, DIV_RESCALE, level, A0, o0);
-  divide(R, DIV_RESCALE, level, A1, o1);
+  // Inner sums for every giant step at once: A = sum_i ct_i f^_i (j = 0) and
+  // S_j = sum_i ct_i f^_{n1 j + i}.
+  {
+    std::vector<MacTerm> terms;
+    std::vector<int> js;
+    std::vector<uint64_t*> out0, out1;
+    for (int j = 0; j < n2; ++j)
+      if (j == 0 || used_j[j]) {
+        js.push_back(j);
+        out0.push_back(j == 0 ? A0 : S0[j]);
+        out1.push_back(j == 0 ? A1 : S1[j]);
+      }
+    for (int i = 0; i < n1; ++i) {
+      if (!used_i[i]) continue;
+      MacTerm t{R0[i], R1[i], false, {}};
+      for (int j : js) t.f.push_back(D.has(n1 * j + i) ? D.pt[n1 * j + i] : nullptr);
+      terms.push_back(t);
+    }
+    if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, std::vector<const uint64_t*>(js.size(), nullptr)});
+    ptmac(R, Lq, P->alpha, terms, out0, out1);
+  }
+  // Giant steps: A += Rot(S_j, n1 j).
+  {
+    std::vector<RotJob> jobs;
+    for (int j = 1; j < n2; ++j)
+      if (used_j[j]) jobs.push_back(RotJob{S0[j], S1[j], (long)n1 * j, A0, A1, true});
+    rotate(R, level, jobs, ks);
+  }
+  divide(R, DIV_RESCALE, level, IOList{{A0, o0}, {A1, o1}});
 }
 
 // ---- diagonal method ---------------------------------------------------------
@@ -449,39 +616,23 @@ void lt_naive(Run& R, int level, const uint64_t* c0, const uint64_t* c1, const D
   const int Lq = level + 1;
   uint64_t* A0 = R.limbs(Lq);
   uint64_t* A1 = R.limbs(Lq);
-  uint64_t* T0 = R.limbs(Lq);
-  uint64_t* T1 = R.limbs(Lq);
-  bool acc_init = false;
-  for (int d = 0; d < D.n; ++d) {
-    if (!D.has(d)) continue;
-    const uint64_t *r0 = c0, *r1 = c1;
-    if (d != 0) {
-      rotate(R, level, c0, c1, d, ks, T0, T1, false);
-      r0 = T0;
-      r1 = T1;
-    }
-    std::vector<MacTerm> t{MacTerm{r0, r1, false, {D.pt[d]}}};
-    // accumulate through a one-term MAC: A += r * f
-    if (!R.dry && !R.err) {
-      MacArgs ma;
-      memset(&ma, 0, sizeof(ma));
-      ma.nm = 1;
-      ma.nk = 1;
-      ma.K = Lq;
-      ma.prime_off = P->alpha;
-      ma.accumulate = acc_init ? 1 : 0;
-      ma.a[0] = r0;
-      ma.b[0] = r1;
-      ma.f[0][0] = D.pt[d];
-      ma.out0[0] = A0;
-      ma.out1[0] = A1;
-      R.check(launch_ptmac(P, ma, R.s));
-    }
-    acc_init = true;
+  std::vector<int> ds;
+  for (int d = 1; d < D.n; ++d)
+    if (D.has(d)) ds.push_back(d);
+  std::vector<uint64_t*> T0(ds.size()), T1(ds.size());
+  for (size_t t = 0; t < ds.size(); ++t) {
+    T0[t] = R.limbs(Lq);
+    T1[t] = R.limbs(Lq);
   }
-  if (!acc_init) ptmac(R, Lq, P->alpha, {MacTerm{c0, c1, false, {nullptr}}}, {A0}, {A1});
-  divide(R, DIV_RESCALE, level, A0, o0);
-  divide(R, DIV_RESCALE, level, A1, o1);
+  std::vector<RotJob> jobs;
+  for (size_t t = 0; t < ds.size(); ++t) jobs.push_back(RotJob{c0, c1, (long)ds[t], T0[t], T1[t], false});
+  rotate(R, level, jobs, ks);
+  std::vector<MacTerm> terms;
+  if (D.has(0)) terms.push_back(MacTerm{c0, c1, false, {D.pt[0]}});
+  for (size_t t = 0; t < ds.size(); ++t) terms.push_back(MacTerm{T0[t], T1[t], false, {D.pt[ds[t]]}});
+  if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, {nullptr}});
+  ptmac(R, Lq, P->alpha, terms, {A0}, {A1});
+  divide(R, DIV_RESCALE, level, IOList{{A0, o0}, {A1, o1}});
 }
 
 // ---- argument checks -----------------------------------------------------------
@@ -722,7 +873,8 @@ int ckks_op_keyswitch(const ckks_params* P, int level, const uint64_t* digits, c
   R.s = (hipStream_t)stream;
   R.N = (size_t)P->n;
   R.dry = false;
-  keyswitch(R, level, digits, {key}, {galois(P, -(long)rot)}, add, false, false, {out_a}, {out_b});
+  keyswitch(R, level, {KsDigit{digits, add, false}}, {KsKey{key, galois(P, -(long)rot)}}, {{{out_a, out_b}}},
+            false);
   return R.err;
 }
 

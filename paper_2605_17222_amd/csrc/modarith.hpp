@@ -75,6 +75,42 @@ __host__ __device__ __forceinline__ uint64_t barrett128(U128 x, uint64_t q, uint
   return csub(x.lo - qhat * q, q);
 }
 
+// ---- exact FP64 arithmetic for primes q < 2^46 ----------------------------
+// Residues are doubles holding exact integers.  A product x*w (0 <= w < q) is
+// reduced with an FMA two-product, so the remainder is exact:
+//   t = rint(x * fl(w/q)),  h + l = t*q exactly,  r = fl(x*w - h) - l.
+// |fl(x fl(w/q)) - x w/q| <= |x| 2^-52, so for |x| <= 16 q < 2^50 we get
+// |x w/q - t| <= 1/2 + 2^-2 and |r| <= 0.75 q; x*w - h = (x*w - t q) + l with
+// |l| <= ulp(h)/2 <= 2^45, so it is an integer below 2^53 and the FMA that
+// forms it is exact.
+
+// x < 2^53 as a double.
+__host__ __device__ __forceinline__ double u64_to_d(uint64_t x) {
+  return fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+}
+
+__host__ __device__ __forceinline__ double fp_mulmod(double x, double w, double wq, double q) {
+  const double t = rint(x * wq);
+  const double h = t * q;
+  const double l = fma(t, q, -h);
+  return fma(x, w, -h) - l;
+}
+
+// |x| < 2^52 -> x mod q in [-q/2 - 1, q/2 + 1] (an exact FMA: the result is below q).
+__host__ __device__ __forceinline__ double fp_reduce(double x, double q, double qinv) {
+  return fma(-rint(x * qinv), q, x);
+}
+
+// |x| < 2^52 -> canonical residue in [0, q) as uint64.
+__host__ __device__ __forceinline__ uint64_t fp_canon(double x, double q, double qinv) {
+  double r = fp_reduce(x, q, qinv);
+  r = r < 0 ? r + q : r;
+  r = r >= q ? r - q : r;
+  const double hi = floor(r * (1.0 / 4294967296.0));
+  const double lo = fma(-hi, 4294967296.0, r);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
 // Bit reversal of the low `bits` bits.
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
 

@@ -17,9 +17,15 @@
 //                independently.
 // Inside a pass each thread keeps 16 words in registers: 4 stages run in
 // registers, the words are exchanged through LDS, and the remaining stages run
-// in registers again.  Butterflies use Harvey's lazy ranges ([0, 4q) forward,
-// [0, 2q) inverse) and Shoup twiddle products; values are made canonical only
-// on the final pass.
+// in registers again.
+//
+// Two arithmetic paths, chosen per limb (uniform over a workgroup):
+//  * integer (q >= 2^48): Harvey's lazy butterflies ([0, 4q) forward,
+//    [0, 2q) inverse) with Shoup twiddle products;
+//  * FP64 (q < 2^48): residues are doubles holding exact integers, the
+//    twiddle product is the exact FMA two-product remainder of modarith.hpp,
+//    values are re-centred every 4 stages.  Between the two passes such a limb
+//    is stored as raw double bits; the final pass writes canonical residues.
 //
 // Stage s of a sub-transform of P = 2^p points whose global twiddle base is B
 // uses twiddle index B 2^s + (x >> (p - s)) for butterfly position x; B = 1
@@ -31,33 +37,23 @@ namespace ckks {
 
 namespace {
 
-template <int P>
-__device__ __forceinline__ int lds_pad(int i) {
-  return i + (i >> 4);
-}
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
-template <int PLOG, int G, bool COL, bool FWD>
-__global__ void __launch_bounds__(G*(1 << PLOG) / 16)
-    ntt_pass(NttArgs args, const PrimeDev* __restrict__ primes, int log_n, int epi,
-             const BConvPlan* __restrict__ plan) {
+__device__ __forceinline__ double as_d(uint64_t u) { return __longlong_as_double((long long)u); }
+__device__ __forceinline__ uint64_t as_u(double d) { return (uint64_t)__double_as_longlong(d); }
+
+template <int PLOG, int G, bool COL, bool FWD, bool FP>
+__device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const PrimeDev& pr, int log_n, int epi,
+                                         const BConvPlan* __restrict__ plan, uint64_t* lds) {
   constexpr int P = 1 << PLOG;
   constexpr int T = P / 16;           // threads per sub-transform
   constexpr int RS = P + P / 16 + 1;  // LDS row stride (padded)
-  __shared__ uint64_t lds[G * RS];
-
-  // Which limb (uniform over the workgroup).
-  int limb = blockIdx.y;
-  int ri = 0;
-  while (ri < args.nr - 1 && limb >= args.r[ri].count) {
-    limb -= args.r[ri].count;
-    ++ri;
-  }
-  const LimbRange& R = args.r[ri];
-  const PrimeDev& pr = primes[R.prime0 + limb];
   const uint64_t q = pr.q, q2 = 2 * q;
+  const double qd = pr.qd, qi = pr.qinv_d;
   const int n = 1 << log_n;
   const uint64_t* __restrict__ tw = pr.tw + (FWD ? 0 : 2 * (size_t)n);
-  const uint64_t* __restrict__ src = ((COL == FWD) ? R.in : R.out) + (size_t)limb * n;
+  const bool first = (COL == FWD);  // first pass of the transform
+  const uint64_t* __restrict__ src = (first ? R.in : R.out) + (size_t)limb * n;
   uint64_t* __restrict__ dst = R.out + (size_t)limb * n;
 
   const int tid = threadIdx.x;
@@ -69,61 +65,36 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
     j = tid % T;
     g = tid / T;
   }
-  const int sub = blockIdx.x * G + g;       // column index (COL) or row index (row pass)
-  const int ncols = n >> PLOG;              // N2 when COL
-  // Global twiddle base of this sub-transform.
+  const int sub = blockIdx.x * G + g;  // column index (column pass) or row index (row pass)
+  const int ncols = n >> PLOG;
   const uint32_t base = COL ? 1u : (uint32_t)((n >> PLOG) + sub);
   uint64_t* L = lds + g * RS;
 
-  uint64_t v[16];
-
+  uint64_t v[16];  // integer residues, or double bits on the FP path
   auto addr = [&](int x) -> size_t { return COL ? (size_t)x * ncols + sub : (size_t)sub * P + x; };
 
-  // Round over local stages [s_lo, s_hi) (forward) in layout "x = j + T u".
-  auto fwd_round1 = [&]() {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int d = 8 >> s;  // u-distance
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if (u & d) continue;
-        const uint32_t ti = (base << s) + (uint32_t)(u >> (4 - s));
-        const uint64_t w = tw[ti], wp = tw[n + ti];
-        uint64_t X = v[u], Y = v[u + d];
+  // One butterfly between registers u and u + d with twiddle index ti.
+  auto bfly = [&](int u, int d, uint32_t ti) {
+    if (FP) {
+      const double w = as_d(tw[ti]), wq = as_d(tw[n + ti]);
+      const double X = as_d(v[u]), Y = as_d(v[u + d]);
+      if (FWD) {
+        const double r = fp_mulmod(Y, w, wq, qd);
+        v[u] = as_u(X + r);
+        v[u + d] = as_u(X - r);
+      } else {
+        v[u] = as_u(X + Y);
+        v[u + d] = as_u(fp_mulmod(X - Y, w, wq, qd));
+      }
+    } else {
+      const uint64_t w = tw[ti], wp = tw[n + ti];
+      if (FWD) {
+        uint64_t X = v[u];
         X = X >= q2 ? X - q2 : X;
-        const uint64_t t = shoup_lazy(Y, w, wp, q);
+        const uint64_t t = shoup_lazy(v[u + d], w, wp, q);
         v[u] = X + t;
         v[u + d] = X - t + q2;
-      }
-    }
-  };
-  // Local stages 4 .. PLOG-1 in layout "x = 16 j + u".
-  auto fwd_round2 = [&]() {
-#pragma unroll
-    for (int s = 4; s < PLOG; ++s) {
-      const int d = P >> (s + 1);
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if (u & d) continue;
-        const uint32_t ti = (base << s) + (uint32_t)((16 * j + u) >> (PLOG - s));
-        const uint64_t w = tw[ti], wp = tw[n + ti];
-        uint64_t X = v[u], Y = v[u + d];
-        X = X >= q2 ? X - q2 : X;
-        const uint64_t t = shoup_lazy(Y, w, wp, q);
-        v[u] = X + t;
-        v[u + d] = X - t + q2;
-      }
-    }
-  };
-  auto inv_round2 = [&]() {
-#pragma unroll
-    for (int s = PLOG - 1; s >= 4; --s) {
-      const int d = P >> (s + 1);
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if (u & d) continue;
-        const uint32_t ti = (base << s) + (uint32_t)((16 * j + u) >> (PLOG - s));
-        const uint64_t w = tw[ti], wp = tw[n + ti];
+      } else {
         const uint64_t X = v[u], Y = v[u + d];
         uint64_t sm = X + Y;
         sm = sm >= q2 ? sm - q2 : sm;
@@ -132,51 +103,68 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
       }
     }
   };
-  auto inv_round1 = [&]() {
+  // Stages 0..3 in layout "x = j + T u" (twiddle index depends on u only).
+  auto round1 = [&]() {
 #pragma unroll
-    for (int s = 3; s >= 0; --s) {
+    for (int k = 0; k < 4; ++k) {
+      const int s = FWD ? k : 3 - k;
       const int d = 8 >> s;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if (u & d) continue;
-        const uint32_t ti = (base << s) + (uint32_t)(u >> (4 - s));
-        const uint64_t w = tw[ti], wp = tw[n + ti];
-        const uint64_t X = v[u], Y = v[u + d];
-        uint64_t sm = X + Y;
-        sm = sm >= q2 ? sm - q2 : sm;
-        v[u] = sm;
-        v[u + d] = shoup_lazy(X - Y + q2, w, wp, q);
-      }
+      for (int u = 0; u < 16; ++u)
+        if (!(u & d)) bfly(u, d, (base << s) + (uint32_t)(u >> (4 - s)));
     }
   };
-  // Exchange layouts through LDS.
-  auto to_lds = [&](bool from_round1) {
+  // Stages 4..PLOG-1 in layout "x = 16 j + u".
+  auto round2 = [&]() {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int x = from_round1 ? (j + T * u) : (16 * j + u);
-      L[lds_pad<P>(x)] = v[u];
-    }
-  };
-  auto from_lds = [&](bool to_round1) {
+    for (int k = 4; k < PLOG; ++k) {
+      const int s = FWD ? k : PLOG - 1 - (k - 4);
+      const int d = P >> (s + 1);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int x = to_round1 ? (j + T * u) : (16 * j + u);
-      v[u] = L[lds_pad<P>(x)];
+      for (int u = 0; u < 16; ++u)
+        if (!(u & d)) bfly(u, d, (base << s) + (uint32_t)((16 * j + u) >> (PLOG - s)));
     }
   };
-  const bool last = (COL != FWD);  // second pass of the transform
+  auto recentre = [&]() {
+    if (FP) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = as_u(fp_reduce(as_d(v[u]), qd, qi));
+    }
+  };
+  auto to_lds = [&](bool layout1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) L[lds_pad(layout1 ? (j + T * u) : (16 * j + u))] = v[u];
+  };
+  auto from_lds = [&](bool layout1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = L[lds_pad(layout1 ? (j + T * u) : (16 * j + u))];
+  };
+  // Canonical residues arrive as integers; the FP path converts them.
+  auto convert_in = [&]() {
+    if (FP) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = as_u(u64_to_d(v[u]));
+    }
+  };
+  // Final values -> canonical residues.
+  auto canon = [&](uint64_t x) -> uint64_t {
+    if (FP) return fp_canon(as_d(x), qd, qi);
+    x = x >= q2 ? x - q2 : x;
+    return csub(x, q);
+  };
 
   if (FWD) {
-    // load in layout j + T u (coalesced for both passes)
 #pragma unroll
     for (int u = 0; u < 16; ++u) v[u] = src[addr(j + T * u)];
-    fwd_round1();
+    if (first) convert_in();
+    round1();
+    recentre();
     to_lds(true);
     __syncthreads();
     from_lds(false);
-    fwd_round2();
+    round2();
     if (COL) {
-      // layout 16 j + u is coalesced across g for the column pass
+      // intermediate of the transform: lazy integers or double bits
 #pragma unroll
       for (int u = 0; u < 16; ++u) dst[addr(16 * j + u)] = v[u];
     } else {
@@ -193,9 +181,7 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int x = j + T * u;
-        uint64_t y = v[u];
-        y = y >= q2 ? y - q2 : y;
-        y = csub(y, q);
+        uint64_t y = canon(v[u]);
         if (epi == EPI_SUBMUL) y = shoup(aux[addr(x)] - y + q, c, cs, q);
         dst[addr(x)] = y;
       }
@@ -207,24 +193,62 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
     } else {
 #pragma unroll
       for (int u = 0; u < 16; ++u) v[u] = src[addr(j + T * u)];
+      if (R.copy) {
+        uint64_t* __restrict__ cp = R.copy + (size_t)limb * n;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) cp[addr(j + T * u)] = v[u];
+      }
       to_lds(true);
       __syncthreads();
       from_lds(false);
       __syncthreads();
     }
-    inv_round2();
+    if (first) convert_in();
+    round2();
+    recentre();
     to_lds(false);
     __syncthreads();
     from_lds(true);
-    inv_round1();
-    if (last) {
+    round1();
+    if (!first) {
+      // last pass: times N^-1, canonical
 #pragma unroll
-      for (int u = 0; u < 16; ++u) dst[addr(j + T * u)] = shoup(v[u], pr.ninv, pr.ninv_sh, q);
+      for (int u = 0; u < 16; ++u) {
+        uint64_t y;
+        if (FP)
+          y = fp_canon(fp_mulmod(as_d(v[u]), pr.ninv_d, pr.ninv_q, qd), qd, qi);
+        else
+          y = shoup(v[u], pr.ninv, pr.ninv_sh, q);
+        dst[addr(j + T * u)] = y;
+      }
     } else {
+      recentre();
 #pragma unroll
       for (int u = 0; u < 16; ++u) dst[addr(j + T * u)] = v[u];
     }
   }
+}
+
+template <int PLOG, int G, bool COL, bool FWD>
+__global__ void __launch_bounds__(G*(1 << PLOG) / 16)
+    ntt_pass(NttArgs args, const PrimeDev* __restrict__ primes, int log_n, int epi,
+             const BConvPlan* __restrict__ plan) {
+  constexpr int P = 1 << PLOG;
+  constexpr int RS = P + P / 16 + 1;
+  __shared__ uint64_t lds[G * RS];
+  // Which limb (uniform over the workgroup).
+  int limb = blockIdx.y;
+  int ri = 0;
+  while (ri < args.nr - 1 && limb >= args.r[ri].count) {
+    limb -= args.r[ri].count;
+    ++ri;
+  }
+  const LimbRange& R = args.r[ri];
+  const PrimeDev& pr = primes[R.prime0 + limb];
+  if (pr.fp)
+    ntt_body<PLOG, G, COL, FWD, true>(R, limb, pr, log_n, epi, plan, lds);
+  else
+    ntt_body<PLOG, G, COL, FWD, false>(R, limb, pr, log_n, epi, plan, lds);
 }
 
 template <int PLOG, bool COL, bool FWD>
@@ -233,12 +257,15 @@ hipError_t launch_pass(const ckks_params* P, const NttArgs& a, int total, int ep
   constexpr int Pn = 1 << PLOG;
   constexpr int G = 4096 / Pn;
   const int n = P->n;
-  const int subs = n >> PLOG;  // columns (COL) or rows
+  const int subs = n >> PLOG;  // columns (column pass) or rows
   if (subs % G) return hipErrorInvalidValue;
   dim3 grid(subs / G, total);
   const int id = FWD ? (COL ? CKKS_KERNEL_NTT_FWD_COL : CKKS_KERNEL_NTT_FWD_ROW)
                      : (COL ? CKKS_KERNEL_NTT_INV_COL : CKKS_KERNEL_NTT_INV_ROW);
-  ProfScope prof(id, s, (double)total * n * 8 * (epi == EPI_SUBMUL ? 3 : 2));
+  double words = (double)total * n * (epi == EPI_SUBMUL ? 3 : 2);
+  if (!FWD && !COL)
+    for (int i = 0; i < a.nr; ++i) words += a.r[i].copy ? (double)a.r[i].count * n : 0;
+  ProfScope prof(id, s, words * 8);
   hipLaunchKernelGGL((ntt_pass<PLOG, G, COL, FWD>), grid, dim3(G * Pn / 16), 0, s, a, P->d_primes, P->log_n,
                      epi, plan);
   return hipGetLastError();

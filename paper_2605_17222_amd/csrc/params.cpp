@@ -157,14 +157,30 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
       a = mm(a, psi, q);
       b = mm(b, psi_inv, q);
     }
+    const bool fp = q < kFpPrimeLimit;
+    auto dbits = [](double x) {
+      uint64_t u;
+      memcpy(&u, &x, 8);
+      return u;
+    };
     for (int k = 0; k < n; ++k) {
       const uint32_t r = brev(k, P->log_n);
-      t[k] = pf[r];
-      t[n + k] = shoup_of(pf[r], q);
-      t[2 * n + k] = pi[r];
-      t[3 * n + k] = shoup_of(pi[r], q);
+      if (fp) {
+        t[k] = dbits((double)pf[r]);
+        t[n + k] = dbits((double)pf[r] / (double)q);
+        t[2 * n + k] = dbits((double)pi[r]);
+        t[3 * n + k] = dbits((double)pi[r] / (double)q);
+      } else {
+        t[k] = pf[r];
+        t[n + k] = shoup_of(pf[r], q);
+        t[2 * n + k] = pi[r];
+        t[3 * n + k] = shoup_of(pi[r], q);
+      }
     }
     PrimeDev& c = pd[i];
+    c.fp = fp ? 1 : 0;
+    c.qd = (double)q;
+    c.qinv_d = 1.0 / (double)q;
     c.q = q;
     c.qinv_neg = neg_inv64(q);
     const u128 r = (~(u128)0) / q;  // floor(2^128 / q): q odd, does not divide 2^128
@@ -172,6 +188,8 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
     c.r_hi = (uint64_t)(r >> 64);
     c.ninv = inv((uint64_t)n % q, q);
     c.ninv_sh = shoup_of(c.ninv, q);
+    c.ninv_d = (double)c.ninv;
+    c.ninv_q = (double)c.ninv / (double)q;
     uint64_t Pm = 1;
     for (int k = 0; k < P->alpha; ++k) Pm = mm(Pm, P->primes[k] % q, q);
     c.pmod = i < P->alpha ? 0 : Pm;

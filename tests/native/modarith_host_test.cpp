@@ -2,6 +2,7 @@
 // integer division, on random and edge-case operands for primes up to 2^61.
 #include <stdio.h>
 #include <stdlib.h>
+#include <math.h>
 
 #include "../../paper_2605_17222_amd/csrc/modarith.hpp"
 
@@ -45,6 +46,32 @@ int main() {
       uint64_t rr = redc(y, q, qn);
       // rr * 2^64 == y mod q
       fails += !(rr < q && (uint64_t)((((u128)rr << 64) % q)) == (uint64_t)(yv % q));
+      checks += 4;
+    }
+  }
+  // exact FP64 arithmetic for q < 2^46: |x| <= 16 q, w in [0, q)
+  const uint64_t fq[] = {1099511922689ull, 1073692673ull, 70368744161281ull, 35184372088321ull};
+  for (uint64_t q : fq) {
+    const double qd = (double)q, qi = 1.0 / qd;
+    for (int it = 0; it < 300000; ++it) {
+      const uint64_t w = rnd() % q;
+      const double wd = (double)w, wq = wd / qd;
+      const int64_t lim = (int64_t)16 * (int64_t)q;
+      int64_t x = (int64_t)(rnd() % (2 * (uint64_t)lim)) - lim;
+      if (it < 3) x = it == 0 ? lim - 1 : (it == 1 ? -lim + 1 : 0);
+      const double r = fp_mulmod((double)x, wd, wq, qd);
+      // r must be an exact integer with r = x*w mod q and |r| <= 1.07 q
+      const __int128 ref = ((__int128)x * (__int128)w) % (__int128)q;
+      const __int128 diff = (__int128)(int64_t)r - ref;
+      fails += (r != (double)(int64_t)r) || (diff % (__int128)q != 0) || (fabs(r) > 0.75 * qd);
+      const double rr = fp_reduce((double)x, qd, qi);
+      fails += (((__int128)(int64_t)rr - x) % (__int128)q != 0) || fabs(rr) > 0.5 * qd + 1;
+      const uint64_t c = fp_canon((double)x, qd, qi);
+      __int128 xm = x % (__int128)q;
+      if (xm < 0) xm += q;
+      fails += c != (uint64_t)xm;
+      const uint64_t u = rnd() % q;
+      fails += u64_to_d(u) != (double)u;
       checks += 4;
     }
   }
