@@ -198,8 +198,10 @@ int ckks_op_automorph(const ckks_params* params, int32_t rot, int n_limbs, const
 
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 /* Kernel identifiers: the forward NTT column / row passes, the inverse NTT
- * row / column passes, basis conversion, key-switch inner product, plaintext
- * multiply-accumulate and the automorphism gather. */
+ * row / column passes, basis conversion, key-switch inner product (several
+ * digit sets and keys, automorphism on write), plaintext multiply-accumulate,
+ * the automorphism gather, and the gather form of the key switch that adds
+ * every outer rotation into the accumulator. */
 #define CKKS_KERNEL_NTT_FWD_COL 0
 #define CKKS_KERNEL_NTT_FWD_ROW 1
 #define CKKS_KERNEL_NTT_INV_ROW 2
@@ -208,7 +210,8 @@ int ckks_op_automorph(const ckks_params* params, int32_t rot, int n_limbs, const
 #define CKKS_KERNEL_KEYSWITCH 5
 #define CKKS_KERNEL_PTMAC 6
 #define CKKS_KERNEL_AUTOMORPH 7
-#define CKKS_KERNEL_COUNT 8
+#define CKKS_KERNEL_KEYSWITCH_GATHER 8
+#define CKKS_KERNEL_COUNT 9
 
 /*
  * Process-wide: for every kernel k with bit (1 << k) set in mask, each later

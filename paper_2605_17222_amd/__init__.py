@@ -36,7 +36,7 @@ EXPORTED = [
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
-           "automorph"]
+           "automorph", "keyswitch_gather"]
 
 
 class CkksError(RuntimeError):

@@ -120,6 +120,10 @@ __global__ void __launch_bounds__(kThreads)
   a.c1[o] = c1;
 }
 
+// m-outer loop: (a_m, b_m) and the NK plaintexts of index m are loaded
+// together and folded into NK pairs of 128-bit accumulators, so few values are
+// live and many loads are in flight per wavefront.
+template <int NK>
 __global__ void __launch_bounds__(kThreads)
     mac_kernel(MacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
@@ -129,33 +133,35 @@ __global__ void __launch_bounds__(kThreads)
   const uint64_t q = pr.q;
   const size_t off = (size_t)l * n + p;
 
-  uint64_t av[kMaxMacM], bv[kMaxMacM];
+  U128 x[NK], y[NK];
 #pragma unroll
-  for (int m = 0; m < kMaxMacM; ++m) {
-    if (m < a.nm) {
-      if (m == 0 && a.pscaled0) {
-        // (a_0, b_0) = (P c0', P c1'): zero on the special primes.
-        const int lq = l + a.prime_off - alpha;
-        av[m] = lq < 0 ? 0 : shoup(a.a[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
-        bv[m] = lq < 0 ? 0 : shoup(a.b[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
-      } else {
-        av[m] = a.a[m][off];
-        bv[m] = a.b[m][off];
+  for (int k = 0; k < NK; ++k) x[k] = y[k] = U128{0, 0};
+#pragma unroll 2
+  for (int m = 0; m < a.nm; ++m) {
+    uint64_t av, bv;
+    if (m == 0 && a.pscaled0) {
+      // (a_0, b_0) = (P c0', P c1'): zero on the special primes.
+      const int lq = l + a.prime_off - alpha;
+      av = lq < 0 ? 0 : shoup(a.a[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
+      bv = lq < 0 ? 0 : shoup(a.b[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
+    } else {
+      av = a.a[m][off];
+      bv = a.b[m][off];
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const uint64_t* __restrict__ fp = a.f[k][m];
+      if (fp) {
+        const uint64_t f = fp[off];
+        add128(x[k], mul_wide(av, f));
+        add128(y[k], mul_wide(bv, f));
       }
     }
   }
-  for (int k = 0; k < a.nk; ++k) {
-    U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
-    for (int m = 0; m < kMaxMacM; ++m) {
-      if (m < a.nm && a.f[k][m]) {
-        const uint64_t f = a.f[k][m][off];
-        add128(x, mul_wide(av[m], f));
-        add128(y, mul_wide(bv[m], f));
-      }
-    }
-    uint64_t xr = barrett128(x, q, pr.r_lo, pr.r_hi);
-    uint64_t yr = barrett128(y, q, pr.r_lo, pr.r_hi);
+  for (int k = 0; k < NK; ++k) {
+    uint64_t xr = barrett128(x[k], q, pr.r_lo, pr.r_hi);
+    uint64_t yr = barrett128(y[k], q, pr.r_lo, pr.r_hi);
     if (a.accumulate) {
       xr = add_mod(xr, a.out0[k][off], q);
       yr = add_mod(yr, a.out1[k][off], q);
@@ -163,6 +169,13 @@ __global__ void __launch_bounds__(kThreads)
     a.out0[k][off] = xr;
     a.out1[k][off] = yr;
   }
+}
+
+template <int NK>
+hipError_t launch_mac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  hipLaunchKernelGGL((mac_kernel<NK>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -204,21 +217,29 @@ hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s
 
 hipError_t launch_keyswitch_gather(const ckks_params* P, const KsGatherArgs& a, hipStream_t s) {
   const double words = (double)a.K * P->n * (4.0 + a.nk * (3.0 * a.beta + 1));
-  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * 8);
+  ProfScope prof(CKKS_KERNEL_KEYSWITCH_GATHER, s, words * 8);
   dim3 grid(P->n / kThreads, a.K);
   hipLaunchKernelGGL(ks_gather_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
   return hipGetLastError();
 }
 
 hipError_t launch_ptmac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
-  dim3 grid(P->n / kThreads, a.K);
   int nf = 0;
   for (int k = 0; k < a.nk; ++k)
     for (int m = 0; m < a.nm; ++m) nf += a.f[k][m] ? 1 : 0;
   const double words = (double)a.K * P->n * (2.0 * a.nm + nf + 2.0 * a.nk * (a.accumulate ? 2 : 1));
   ProfScope prof(CKKS_KERNEL_PTMAC, s, words * 8);
-  hipLaunchKernelGGL(mac_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
-  return hipGetLastError();
+  switch (a.nk) {
+    case 1: return launch_mac<1>(P, a, s);
+    case 2: return launch_mac<2>(P, a, s);
+    case 3: return launch_mac<3>(P, a, s);
+    case 4: return launch_mac<4>(P, a, s);
+    case 5: return launch_mac<5>(P, a, s);
+    case 6: return launch_mac<6>(P, a, s);
+    case 7: return launch_mac<7>(P, a, s);
+    case 8: return launch_mac<8>(P, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_automorph(const ckks_params* P, const AutoArgs& a, hipStream_t s) {
