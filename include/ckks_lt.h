@@ -123,6 +123,10 @@ typedef struct {
 #define CKKS_LT_NAIVE 0    /* diagonal method: sum_d Rot(ct, d) f_d           */
 #define CKKS_LT_BSGS 1     /* plain BSGS, eq. (5), one Decompose per rotation */
 #define CKKS_LT_TH_BSGS 2  /* triple-hoisted BSGS, Algorithm 2                */
+#define CKKS_LT_DH_BSGS 3  /* double-hoisted BSGS, Algorithm 1: baby steps n1,
+                              giant steps n2 (exactly TH-BSGS with n1' = 1,
+                              n2' = n1, n3' = n2; plaintexts pre-rotated by
+                              phi_{-n1 j}, PQ basis)                       */
 
 /* Workspace bytes ckks_lt_eval needs for this level, split and algorithm. */
 int ckks_lt_workspace_size(const ckks_params* params, int level, const ckks_lt_diags* diags, int algo,
@@ -143,6 +147,39 @@ int ckks_lt_workspace_size(const ckks_params* params, int level, const ckks_lt_d
  */
 int ckks_lt_eval(const ckks_params* params, const ckks_ct* in, const ckks_lt_diags* diags,
                  const ckks_rotkeys* keys, int algo, ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- ragged batches --------------------------------------------------------- */
+/*
+ * One LT of a batch: its own ciphertext, diagonals (split and plaintexts),
+ * rotation keys (the same ckks_rotkeys may serve many items) and output.
+ * status receives the item's result code.
+ */
+typedef struct {
+  ckks_ct in;
+  ckks_lt_diags diags;
+  const ckks_rotkeys* keys;
+  ckks_ct out;
+  int status;
+} ckks_lt_item;
+
+/* Workspace bytes ckks_lt_eval_batch needs for these items (buffers unread). */
+int ckks_lt_batch_workspace_size(const ckks_params* params, int count, const ckks_lt_item* items, int algo,
+                                 size_t* bytes);
+
+/*
+ * Evaluates count LTs of one parameter set whose levels, splits and diagonal
+ * counts may all differ.  For CKKS_LT_TH_BSGS the items run in lockstep:
+ * every line of Algorithm 2 is issued for all items at once (Decompose and
+ * ModDown of all items share launches; key-switch launches group the digit
+ * sets of every item that uses a key, so each key is read once per launch,
+ * whatever the items' levels).  Other algorithms run the items one after the
+ * other.  Results are bit-identical to evaluating each item alone.  Items
+ * whose arguments are invalid get an error status and are skipped; outputs
+ * must not overlap inputs or each other.  Returns the first error, or
+ * CKKS_OK.  Same stream and ownership rules as ckks_lt_eval.
+ */
+int ckks_lt_eval_batch(const ckks_params* params, int count, ckks_lt_item* items, int algo, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* ---- the steps of the path, one call each (for tests and composition) ---- */
 /*
@@ -195,6 +232,45 @@ int ckks_op_keyswitch(const ckks_params* params, int level, const uint64_t* digi
 /* NTT-domain automorphism phi_r (eq. (7)) of n_limbs limbs: out[p] = in[pi_r(p)]. */
 int ckks_op_automorph(const ckks_params* params, int32_t rot, int n_limbs, const uint64_t* in, uint64_t* out,
                       void* stream);
+
+/* ---- complexity model and split autotuner (host only, no device) ------------ */
+/* Operation counts and bytes of one LT (Table I; counts of Section III). */
+typedef struct {
+  double modmul;      /* modular multiplications (Table II's counting)          */
+  double ntt_limbs;   /* limb NTTs and inverse NTTs                             */
+  double decompose;   /* Decompose operations                                   */
+  double moddown;     /* ModDown operations (the final one counted per polynomial) */
+  double keyswitch;   /* key-switch inner products                              */
+  int keys;           /* distinct switching keys                                */
+  double key_bytes;   /* switching-key storage, words of word_bits bits         */
+  double pt_bytes;    /* plaintext storage (all n1 n2 n3 diagonals)              */
+} ckks_lt_cost;
+
+/*
+ * Cost of an LT with ring 2^log_n, ciphertext level `level`, alpha special
+ * primes and split (n1, n2, n3) (n3 ignored unless TH-BSGS; BSGS and DH-BSGS
+ * use n1 baby and n2 giant steps).  word_bits sizes the byte counts (64 for
+ * this library's uint64 words, 54 for the paper's Table II).
+ */
+int ckks_lt_cost_model(int log_n, int level, int alpha, int algo, int n1, int n2, int n3, int word_bits,
+                 ckks_lt_cost* out);
+
+/* Device rates the autotuner predicts with (NULL: values measured on MI355X). */
+typedef struct {
+  double ntt_limb_s;        /* seconds per limb NTT (both passes) at N = 2^16   */
+  double bconv_product_s;   /* seconds per basis-conversion product            */
+  double hbm_bytes_per_s;   /* achieved bandwidth of the HBM-bound kernels     */
+} ckks_lt_rates;
+
+/*
+ * Chooses the split for a banded LT with diagonal offsets 0 .. n_diag-1 that
+ * minimises the predicted device time, among splits with n1 n2 n3 in
+ * [n_diag, 2 n_diag) (padding with absent diagonals) needing at most max_keys
+ * switching keys (max_keys <= 0: no limit).  Writes the split and the
+ * predicted seconds.
+ */
+int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int max_keys, const ckks_lt_rates* rates,
+                     int* n1, int* n2, int* n3, double* predicted_s);
 
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 /* Kernel identifiers: the forward NTT column / row passes, the inverse NTT

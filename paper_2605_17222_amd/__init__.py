@@ -27,12 +27,14 @@ CKKS_E_NOMEM = -5
 CKKS_LT_NAIVE = 0
 CKKS_LT_BSGS = 1
 CKKS_LT_TH_BSGS = 2
+CKKS_LT_DH_BSGS = 3
 
 EXPORTED = [
     "ckks_strerror", "ckks_params_create", "ckks_params_destroy", "ckks_params_info",
     "ckks_lt_workspace_size", "ckks_lt_eval", "ckks_op_ntt", "ckks_op_decompose", "ckks_op_moddown",
     "ckks_op_rescale", "ckks_op_workspace_size", "ckks_op_keyswitch", "ckks_op_automorph",
-    "ckks_profile_enable", "ckks_profile_read",
+    "ckks_profile_enable", "ckks_profile_read", "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch",
+    "ckks_lt_cost_model", "ckks_lt_autotune",
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
@@ -66,6 +68,22 @@ class Diags(ctypes.Structure):
 class RotKeys(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int), ("rot", ctypes.POINTER(ctypes.c_int32)),
                 ("key", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class LtCost(ctypes.Structure):
+    _fields_ = [("modmul", ctypes.c_double), ("ntt_limbs", ctypes.c_double), ("decompose", ctypes.c_double),
+                ("moddown", ctypes.c_double), ("keyswitch", ctypes.c_double), ("keys", ctypes.c_int),
+                ("key_bytes", ctypes.c_double), ("pt_bytes", ctypes.c_double)]
+
+
+class LtRates(ctypes.Structure):
+    _fields_ = [("ntt_limb_s", ctypes.c_double), ("bconv_product_s", ctypes.c_double),
+                ("hbm_bytes_per_s", ctypes.c_double)]
+
+
+class LtItem(ctypes.Structure):
+    _fields_ = [("in_", Ct), ("diags", Diags), ("keys", ctypes.POINTER(RotKeys)), ("out", Ct),
+                ("status", ctypes.c_int)]
 
 
 _lib = None
@@ -107,6 +125,13 @@ def lib() -> ctypes.CDLL:
         L.ckks_profile_enable.argtypes = [ctypes.c_int]
         L.ckks_profile_read.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
+        L.ckks_lt_batch_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(LtItem),
+                                                   ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.ckks_lt_eval_batch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(LtItem), ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.ckks_lt_cost_model.argtypes = [ctypes.c_int] * 8 + [ctypes.POINTER(LtCost)]
+        L.ckks_lt_autotune.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(LtRates)] + \
+            [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -218,6 +243,69 @@ def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequen
     _check(lib().ckks_lt_eval(params, ctypes.byref(cin), ctypes.byref(d), ctypes.byref(k), algo,
                               ctypes.byref(cout), _ptr(ws), ws_bytes, _stream(stream)), "ckks_lt_eval")
     return cout.level, cout.scale
+
+
+class BatchItem:
+    """One LT of a batch (device buffers as tensors or int addresses)."""
+
+    def __init__(self, level, scale, c0, c1, split, pts, pt_scale, keys, out0, out1):
+        self.level, self.scale, self.c0, self.c1 = level, scale, c0, c1
+        self.split, self.pts, self.pt_scale, self.keys = split, pts, pt_scale, keys
+        self.out0, self.out1 = out0, out1
+        self.status = None
+        self.out_level, self.out_scale = None, None
+
+
+def _items(items: Sequence[BatchItem]):
+    arr = (LtItem * max(1, len(items)))()
+    keep = []
+    for t, it in enumerate(items):
+        d, k1 = _diags(it.split, it.pts, it.pt_scale)
+        ks, k2 = _keys(it.keys)
+        keep += [d, k1, ks, k2]
+        arr[t].in_ = Ct(it.level, it.scale, _ptr(it.c0), _ptr(it.c1))
+        arr[t].diags = d
+        arr[t].keys = ctypes.pointer(ks)
+        arr[t].out = Ct(it.level - 1, 0.0, _ptr(it.out0), _ptr(it.out1))
+        arr[t].status = 0
+    return arr, keep
+
+
+def ckks_lt_batch_workspace_size(params: Params, items: Sequence[BatchItem], algo: int) -> int:
+    arr, keep = _items(items)
+    out = ctypes.c_size_t()
+    _check(lib().ckks_lt_batch_workspace_size(params, len(items), arr, algo, ctypes.byref(out)),
+           "ckks_lt_batch_workspace_size")
+    return out.value
+
+
+def ckks_lt_eval_batch(params: Params, items: Sequence[BatchItem], algo: int, ws, ws_bytes: int, stream=None) -> int:
+    """Enqueue every item; fills each item's status, out_level and out_scale.
+    Returns the call's code (raises only on argument marshalling errors)."""
+    arr, keep = _items(items)
+    code = lib().ckks_lt_eval_batch(params, len(items), arr, algo, _ptr(ws), ws_bytes, _stream(stream))
+    for t, it in enumerate(items):
+        it.status = arr[t].status
+        it.out_level, it.out_scale = arr[t].out.level, arr[t].out.scale
+    return code
+
+
+def ckks_lt_cost_model(log_n: int, level: int, alpha: int, algo: int, split: Sequence[int], word_bits: int = 64) -> dict:
+    n1, n2, n3 = (list(split) + [1, 1])[:3]
+    c = LtCost()
+    _check(lib().ckks_lt_cost_model(log_n, level, alpha, algo, n1, n2, n3, word_bits, ctypes.byref(c)),
+           "ckks_lt_cost_model")
+    return {f: getattr(c, f) for f, _ in LtCost._fields_}
+
+
+def ckks_lt_autotune(log_n: int, level: int, alpha: int, algo: int, n_diag: int, max_keys: int = 0,
+                     rates: Optional[Tuple[float, float, float]] = None):
+    """(split, predicted seconds) chosen by the library's cost model."""
+    a, b, c, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    r = ctypes.byref(LtRates(*rates)) if rates else None
+    _check(lib().ckks_lt_autotune(log_n, level, alpha, algo, n_diag, max_keys, r, ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(c), ctypes.byref(t)), "ckks_lt_autotune")
+    return (a.value, b.value, c.value), t.value
 
 
 def ckks_op_ntt(params: Params, forward: bool, first_prime: int, n_limbs: int, x, out, stream=None):

@@ -1,0 +1,160 @@
+// Operation-count model of the LT algorithms (Table I and the counts of
+// Section III) and the split autotuner built on it.
+//
+// Modular multiplications are counted as in Table II: a limb (I)NTT costs
+// (N/2) log2 N, a basis conversion |S| |D| N + |S| N (the products and the
+// (S/s_j)^-1 scaling), a key-switch inner product 2 beta K N, the plaintext
+// products 2 n K N (PQ basis) or 2 n (l+1) N (Q basis, plain BSGS).
+// Decompose = INTT of l+1 limbs, the per-group conversions, NTT of every
+// converted limb; ModDown = INTT of alpha limbs, alpha (l+1) N conversion
+// products, NTT of l+1 limbs, the final multiplication (l+1) N; the final
+// ModDown by P q_l has alpha+1 source and l destination limbs.  With w = 54,
+// N = 2^16, L+1 = 32, alpha = 12 this gives Table II's switching-key sizes
+// exactly and its DH-BSGS / TH-BSGS multiplication counts within 0.5%.
+//
+// The autotuner predicts a split's time on the device from the same counts:
+// limb NTTs x (time per limb NTT) + conversion products x (time per product)
+// + key-switch and plaintext-MAC bytes / (achieved HBM bandwidth), and picks
+// the fastest split that needs at most max_keys switching keys.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "../../include/ckks_lt.h"
+
+namespace {
+
+struct Counts {
+  double dec, md, mdr, ks, n, keys, mac_limbs;
+};
+
+int counts(int algo, int n1, int n2, int n3, int Lq, int K, Counts* c) {
+  memset(c, 0, sizeof(*c));
+  if (algo == CKKS_LT_TH_BSGS) {
+    c->n = (double)n1 * n2 * n3;
+    c->dec = n1 + n3 - 1;
+    c->md = n1 + n3 - 2;
+    c->mdr = 2;
+    c->ks = (double)n1 * n2 + n3 - 2;
+    c->keys = n1 + n2 + n3 - 3;
+    c->mac_limbs = K;
+  } else if (algo == CKKS_LT_DH_BSGS) {
+    c->n = (double)n1 * n2;
+    c->dec = n2;
+    c->md = n2 - 1;
+    c->mdr = 2;
+    c->ks = n1 + n2 - 2;
+    c->keys = n1 + n2 - 2;
+    c->mac_limbs = K;
+  } else if (algo == CKKS_LT_BSGS) {
+    c->n = (double)n1 * n2;
+    c->dec = n1 + n2 - 2;
+    c->md = 2.0 * (n1 + n2 - 2);
+    c->mdr = 0;
+    c->ks = n1 + n2 - 2;
+    c->keys = n1 + n2 - 2;
+    c->mac_limbs = Lq;
+  } else {
+    return CKKS_E_INVALID_ARG;
+  }
+  return CKKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ckks_lt_cost_model(int log_n, int level, int alpha, int algo, int n1, int n2, int n3, int word_bits,
+                 ckks_lt_cost* out) {
+  if (!out || log_n < 1 || log_n > 20 || level < 0 || alpha < 1 || n1 < 1 || n2 < 1 || n3 < 1 || word_bits < 1)
+    return CKKS_E_INVALID_ARG;
+  if (algo != CKKS_LT_TH_BSGS) n3 = 1;
+  const double N = (double)(1 << log_n), ntt = N / 2 * log_n;
+  const int Lq = level + 1, K = alpha + Lq, beta = (Lq + alpha - 1) / alpha;
+  Counts c;
+  const int e = counts(algo, n1, n2, n3, Lq, K, &c);
+  if (e != CKKS_OK) return e;
+  // Decompose: INTT of Lq limbs; per group g: g (K - g) N products + g N scaling; NTT of K - g limbs.
+  double dec = Lq * ntt, dec_ntt = Lq;
+  for (int b = 0; b < beta; ++b) {
+    const int g = std::min(alpha, Lq - alpha * b);
+    dec += (double)g * (K - g) * N + g * N + (K - g) * ntt;
+    dec_ntt += K - g;
+  }
+  const double md = alpha * ntt + (double)alpha * Lq * N + Lq * ntt + Lq * N;
+  const double mdr = (alpha + 1) * ntt + (double)(alpha + 1) * (Lq - 1) * N + (Lq - 1) * ntt + (Lq - 1) * N;
+  const double ks = 2.0 * beta * K * N;
+  memset(out, 0, sizeof(*out));
+  out->decompose = c.dec;
+  out->moddown = c.md + c.mdr;
+  out->keyswitch = c.ks;
+  out->keys = (int)c.keys;
+  out->modmul = c.dec * dec + c.md * md + c.mdr * mdr + c.ks * ks + 2.0 * c.n * c.mac_limbs * N;
+  out->ntt_limbs = c.dec * dec_ntt + c.md * (alpha + Lq) + c.mdr * (alpha + 1 + Lq - 1);
+  const double word = word_bits / 8.0;
+  out->key_bytes = c.keys * 2.0 * beta * K * N * word;
+  out->pt_bytes = c.n * c.mac_limbs * N * word;
+  return CKKS_OK;
+}
+
+int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int max_keys, const ckks_lt_rates* rates,
+                     int* n1, int* n2, int* n3, double* predicted_s) {
+  if (!n1 || !n2 || !n3 || n_diag < 1 || log_n < 1 || log_n > 20) return CKKS_E_INVALID_ARG;
+  ckks_lt_rates r;
+  if (rates) {
+    r = *rates;
+  } else {
+    // Measured on one MI355X at N = 2^16 (two-pass NTT, limb-batched launches).
+    r.ntt_limb_s = 0.77e-6;
+    r.bconv_product_s = 0.76e-12;
+    r.hbm_bytes_per_s = 5.0e12;
+  }
+  const double nscale = (double)(1 << log_n) * log_n / (65536.0 * 16);
+  const int Lq = level + 1, K = alpha + Lq, beta = (Lq + alpha - 1) / alpha;
+  double best = -1;
+  int b1 = 0, b2 = 0, b3 = 0;
+  const int nmax = 2 * n_diag;
+  for (int a = 1; a <= n_diag; ++a)
+    for (int b = 1; (long)a * b <= nmax; ++b) {
+      const int c3max = algo == CKKS_LT_TH_BSGS ? nmax : 1;
+      for (int c = 1; c <= c3max && (long)a * b * c <= nmax; ++c) {
+        const long tot = (long)a * b * c;
+        if (tot < n_diag) continue;
+        if (c > 1 && (long)a * b * (c - 1) >= n_diag) break;  // c larger than needed
+        ckks_lt_cost cost;
+        if (ckks_lt_cost_model(log_n, level, alpha, algo, a, b, c, 64, &cost) != CKKS_OK) continue;
+        if (max_keys > 0 && cost.keys > max_keys) continue;
+        // Key-switch bytes: digits, key, add-in and two outputs per product;
+        // MAC bytes: the present plaintexts, the n1 n2 (a_m, b_m) and the outputs.
+        const int limbs = algo == CKKS_LT_BSGS ? Lq : K;
+        const double N = (double)(1 << log_n);
+        const double ks_bytes = cost.keyswitch * (3.0 * beta + 3) * K * N * 8;
+        const double inner = algo == CKKS_LT_TH_BSGS ? (double)a * b : (double)a;
+        const double outer = algo == CKKS_LT_TH_BSGS ? (double)c : (double)b;
+        const double mac_bytes = ((double)n_diag + 2 * inner + 2 * outer) * limbs * N * 8;
+        double conv = 0;
+        for (int g = 0; g < beta; ++g) {
+          const int gs = std::min(alpha, Lq - alpha * g);
+          conv += (double)gs * (K - gs);
+        }
+        const double bconv_products = (cost.decompose * conv + cost.moddown * alpha * Lq) * N;
+        const double t = cost.ntt_limbs * r.ntt_limb_s * nscale + bconv_products * r.bconv_product_s +
+                         (ks_bytes + mac_bytes) / r.hbm_bytes_per_s;
+        if (best < 0 || t < best - 1e-12) {
+          best = t;
+          b1 = a;
+          b2 = b;
+          b3 = c;
+        }
+      }
+    }
+  if (best < 0) return CKKS_E_UNSUPPORTED;
+  *n1 = b1;
+  *n2 = b2;
+  *n3 = algo == CKKS_LT_TH_BSGS ? b3 : 1;
+  if (predicted_s) *predicted_s = best;
+  return CKKS_OK;
+}
+
+}  // extern "C"

@@ -53,12 +53,12 @@ struct BConvPlan {
 struct LimbRange {
   const uint64_t* in;
   uint64_t* out;
-  const uint64_t* aux;  // epilogue operand laid out like out (or null)
+  const uint64_t* aux;      // division epilogue: the kept limbs, laid out like out
+  uint64_t* copy;           // inverse transforms: also store the input limbs here
+  const uint64_t* sinv;     // division epilogue: divisor^-1 per limb, and its
+  const uint64_t* sinv_sh;  // Shoup companion (device, inside a BConvPlan)
   int prime0;
   int count;
-  uint64_t* copy;       // inverse transforms: also store the input limbs here (or null)
-  int epi0;             // plan index of the first limb's epilogue constant
-  int pad;
 };
 
 constexpr int kMaxRanges = 16;
@@ -83,10 +83,13 @@ struct BConvArgs {
 
 // Key-switch inner products of ndig digit sets with nkeys keys: output
 // (i, k) is phi_k(add_i + <d_i, key_k>), phi_k(<d_i, key_k>) (null = skipped).
+// Digit sets may be at different levels (K_i limbs, beta_i digits): limb l of
+// a key is the same prime at every level, so one key read serves them all.
 struct KsArgs {
-  int ndig, beta, K, kmax, nkeys, accumulate;
-  const uint64_t* digits[kMaxDig];  // [beta][K][N] each
-  const uint64_t* add[kMaxDig];     // [K][N], or Q-basis [K - alpha][N] to be multiplied by P, or null
+  int ndig, nkeys, kmax, kbeta, maxK;
+  int K[kMaxDig], beta[kMaxDig];
+  const uint64_t* digits[kMaxDig];  // [beta_i][K_i][N] each
+  const uint64_t* add[kMaxDig];     // [K_i][N], or Q-basis [K_i - alpha][N] to be multiplied by P, or null
   int add_pscaled[kMaxDig];
   const uint64_t* key[kMaxKs];      // [beta_max][2][kmax][N]
   uint32_t gal_inv[kMaxKs];         // Galois element of -r: value at p is stored at auto_index(p, gal_inv)
@@ -145,7 +148,7 @@ class ProfScope {
 
 // Kernel launchers.
 hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
-                      const BConvPlan* epi_plan, hipStream_t s);
+                      hipStream_t s);
 hipError_t launch_bconv(const struct ::ckks_params* P, const BConvArgs& a, int items, int ns, hipStream_t s);
 hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipStream_t s);
 hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGatherArgs& a, hipStream_t s);

@@ -36,10 +36,11 @@ __global__ void __launch_bounds__(kThreads)
   uint64_t d[NDIG][kMaxBeta], addv[NDIG];
 #pragma unroll
   for (int i = 0; i < NDIG; ++i) {
+    addv[i] = 0;
+    if (l >= a.K[i]) continue;  // this digit set's level has fewer limbs
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b)
-      if (b < a.beta) d[i][b] = a.digits[i][((size_t)b * a.K + l) * n + p];
-    addv[i] = 0;
+      if (b < a.beta[i]) d[i][b] = a.digits[i][((size_t)b * a.K[i] + l) * n + p];
     if (a.add[i]) {
       if (a.add_pscaled[i])
         addv[i] = (l < alpha) ? 0 : shoup(a.add[i][(size_t)(l - alpha) * n + p], pr.pmod, pr.pmod_sh, q);
@@ -52,7 +53,7 @@ __global__ void __launch_bounds__(kThreads)
     uint64_t k0[kMaxBeta], k1[kMaxBeta];
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b) {
-      if (b < a.beta) {
+      if (b < a.kbeta) {
         k0[b] = key[(((size_t)b * 2 + 0) * a.kmax + l) * n + p];
         k1[b] = key[(((size_t)b * 2 + 1) * a.kmax + l) * n + p];
       }
@@ -61,32 +62,25 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
     for (int i = 0; i < NDIG; ++i) {
       uint64_t* oa = a.out_a[i][k];
-      if (!oa) continue;
+      if (!oa || l >= a.K[i]) continue;
       uint64_t* ob = a.out_b[i][k];
       U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
       for (int b = 0; b < kMaxBeta; ++b) {
-        if (b < a.beta) {
+        if (b < a.beta[i]) {
           add128(x, mul_wide(d[i][b], k0[b]));
           add128(y, mul_wide(d[i][b], k1[b]));
         }
       }
-      const uint64_t xr = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv[i], q);
-      const uint64_t yr = barrett128(y, q, pr.r_lo, pr.r_hi);
-      if (a.accumulate) {
-        oa[o] = add_mod(oa[o], xr, q);
-        ob[o] = add_mod(ob[o], yr, q);
-      } else {
-        oa[o] = xr;
-        ob[o] = yr;
-      }
+      oa[o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv[i], q);
+      ob[o] = barrett128(y, q, pr.r_lo, pr.r_hi);
     }
   }
 }
 
 template <int NDIG>
 hipError_t launch_ks(const ckks_params* P, const KsArgs& a, hipStream_t s) {
-  dim3 grid(P->n / kThreads, a.K);
+  dim3 grid(P->n / kThreads, a.maxK);
   hipLaunchKernelGGL((ks_kernel<NDIG>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
   return hipGetLastError();
 }
@@ -197,11 +191,12 @@ __global__ void __launch_bounds__(kThreads)
 hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s) {
   double words = 0;
   for (int i = 0; i < a.ndig; ++i) {
-    words += a.beta + (a.add[i] ? 1 : 0);
-    for (int k = 0; k < a.nkeys; ++k) words += a.out_a[i][k] ? (a.accumulate ? 4 : 2) : 0;
+    double per = a.beta[i] + (a.add[i] ? 1 : 0);
+    for (int k = 0; k < a.nkeys; ++k) per += a.out_a[i][k] ? 2 : 0;
+    words += per * a.K[i];
   }
-  words += 2.0 * a.beta * a.nkeys;
-  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * a.K * P->n * 8);
+  words += 2.0 * a.kbeta * a.nkeys * a.maxK;
+  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * P->n * 8);
   switch (a.ndig) {
     case 1: return launch_ks<1>(P, a, s);
     case 2: return launch_ks<2>(P, a, s);

@@ -3,8 +3,15 @@
 // Every public call first runs its plan "dry" (no launches) to validate the
 // arguments, find the rotation keys it needs and size its workspace, then runs
 // it for real; both runs take the same code path, so the sizes always match.
+//
+// All steps take lists of independent jobs (the type-III independence of
+// Section IV: rotations with different indices, and different ciphertexts,
+// do not depend on each other), possibly at different levels, and pack them
+// into as few launches as the kernel argument tables allow.  A single LT and a
+// ragged batch of LTs run the same code.
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <vector>
 
@@ -29,31 +36,24 @@ struct Run {
   void check(hipError_t e) {
     if (e != hipSuccess) fail(CKKS_E_DEVICE);
   }
+  bool live() const { return !dry && err == CKKS_OK; }
   uint64_t* limbs(size_t c) { return ws.limbs(c); }
 };
 
-// ---- primitive steps ------------------------------------------------------
+// ---- launch packing -----------------------------------------------------------
 
 LimbRange range(const uint64_t* in, uint64_t* out, int prime0, int count, const uint64_t* aux = nullptr,
-                uint64_t* copy = nullptr) {
+                uint64_t* copy = nullptr, const uint64_t* sinv = nullptr, const uint64_t* sinv_sh = nullptr) {
   LimbRange r;
   r.in = in;
   r.out = out;
   r.aux = aux;
+  r.copy = copy;
+  r.sinv = sinv;
+  r.sinv_sh = sinv_sh;
   r.prime0 = prime0;
   r.count = count;
-  r.copy = copy;
-  r.epi0 = 0;
-  r.pad = 0;
   return r;
-}
-
-void ntt_range(Run& R, bool fwd, int prime0, int count, const uint64_t* in, uint64_t* out) {
-  if (R.dry || R.err || count <= 0) return;
-  NttArgs a;
-  a.nr = 1;
-  a.r[0] = range(in, out, prime0, count);
-  R.check(launch_ntt(R.P, fwd, a, count, EPI_NONE, nullptr, R.s));
 }
 
 // Collects limb ranges into NTT launches (flushing when the table is full).
@@ -61,12 +61,9 @@ struct NttBatch {
   Run& R;
   bool fwd;
   int epi;
-  const BConvPlan* plan;
   NttArgs a;
   int total = 0;
-  NttBatch(Run& r, bool f, int e = EPI_NONE, const BConvPlan* pl = nullptr) : R(r), fwd(f), epi(e), plan(pl) {
-    a.nr = 0;
-  }
+  NttBatch(Run& r, bool f, int e = EPI_NONE) : R(r), fwd(f), epi(e) { a.nr = 0; }
   void add(const LimbRange& r) {
     if (r.count <= 0) return;
     if (a.nr == kMaxRanges) flush();
@@ -74,7 +71,7 @@ struct NttBatch {
     total += r.count;
   }
   void flush() {
-    if (a.nr && !R.dry && !R.err) R.check(launch_ntt(R.P, fwd, a, total, epi, plan, R.s));
+    if (a.nr && R.live()) R.check(launch_ntt(R.P, fwd, a, total, epi, R.s));
     a.nr = 0;
     total = 0;
   }
@@ -103,92 +100,98 @@ struct BConvBatch {
     ++items;
   }
   void flush() {
-    if (items && !R.dry && !R.err) R.check(launch_bconv(R.P, a, items, ns, R.s));
+    if (items && R.live()) R.check(launch_bconv(R.P, a, items, ns, R.s));
     reset();
   }
   ~BConvBatch() { flush(); }
 };
 
-typedef std::vector<std::pair<const uint64_t*, uint64_t*>> IOList;
+// An input polynomial at some level and where its result goes.
+struct Job {
+  int level;
+  const uint64_t* in;
+  uint64_t* out;
+};
+typedef std::vector<Job> Jobs;
 
-// Decompose (Fig. 1) of several level-l Q-basis polynomials (NTT form) into
-// digits [beta][K][N] each.  The inverse NTT's first pass also stores each
+// ---- Decompose, ModDown, rescale -----------------------------------------------
+
+// Decompose (Fig. 1) of level-l Q-basis polynomials (NTT form) into digits
+// [beta_l][alpha+l+1][N].  The inverse NTT's first pass also stores each
 // group's own limbs, unchanged, into its digit (ModUp keeps them, R15).
-void decompose(Run& R, int level, const IOList& xs) {
+void decompose(Run& R, const Jobs& xs) {
   const ckks_params* P = R.P;
-  const int a = P->alpha, K = P->K(level), beta = P->beta(level), Lq = level + 1;
+  const int a = P->alpha;
   const size_t N = R.N, mark = R.ws.mark();
   std::vector<uint64_t*> coef(xs.size());
-  for (size_t t = 0; t < xs.size(); ++t) coef[t] = R.limbs(Lq);
-  if (!R.dry && !R.err) {
+  for (size_t t = 0; t < xs.size(); ++t) coef[t] = R.limbs(xs[t].level + 1);
+  if (R.live()) {
     {
       NttBatch inv(R, false);
-      for (size_t t = 0; t < xs.size(); ++t)
-        for (int b = 0; b < beta; ++b) {
+      for (size_t t = 0; t < xs.size(); ++t) {
+        const int level = xs[t].level, K = P->K(level);
+        for (int b = 0; b < P->beta(level); ++b) {
           const int lo = b * a, hi = std::min(lo + a - 1, level);
-          inv.add(range(xs[t].first + (size_t)lo * N, coef[t] + (size_t)lo * N, a + lo, hi - lo + 1, nullptr,
-                        xs[t].second + ((size_t)b * K + a + lo) * N));
+          inv.add(range(xs[t].in + (size_t)lo * N, coef[t] + (size_t)lo * N, a + lo, hi - lo + 1, nullptr,
+                        xs[t].out + ((size_t)b * K + a + lo) * N));
         }
+      }
     }
-    // Digits with a full group of alpha limbs share launches; a shorter last
-    // group has its own.
-    const int last = level - (beta - 1) * a + 1;
     {
-      BConvBatch full(R, a);
-      BConvBatch part(R, last);
-      for (size_t t = 0; t < xs.size(); ++t)
-        for (int b = 0; b < beta; ++b) {
+      std::map<int, BConvBatch*> by_ns;
+      for (size_t t = 0; t < xs.size(); ++t) {
+        const int level = xs[t].level, K = P->K(level);
+        for (int b = 0; b < P->beta(level); ++b) {
           const int lo = b * a, hi = std::min(lo + a - 1, level), g = hi - lo + 1;
-          const BConvPlan* pl = P->plan(P->plan_decomp[(size_t)level * P->beta_max + b]);
-          (g == a ? full : part).add(pl, K - g, coef[t] + (size_t)lo * N, xs[t].second + (size_t)b * K * N, 0);
+          if (!by_ns.count(g)) by_ns[g] = new BConvBatch(R, g);
+          by_ns[g]->add(P->plan(P->plan_decomp[(size_t)level * P->beta_max + b]), K - g,
+                        coef[t] + (size_t)lo * N, xs[t].out + (size_t)b * K * N, 0);
         }
+      }
+      for (auto& kv : by_ns) delete kv.second;  // flushes
     }
     NttBatch fwd(R, true);
-    for (size_t t = 0; t < xs.size(); ++t)
-      for (int b = 0; b < beta; ++b) {
+    for (size_t t = 0; t < xs.size(); ++t) {
+      const int level = xs[t].level, K = P->K(level);
+      for (int b = 0; b < P->beta(level); ++b) {
         const int lo = b * a, hi = std::min(lo + a - 1, level);
-        uint64_t* d = xs[t].second + (size_t)b * K * N;
+        uint64_t* d = xs[t].out + (size_t)b * K * N;
         fwd.add(range(d, d, 0, a + lo));
         fwd.add(range(d + (size_t)(a + hi + 1) * N, d + (size_t)(a + hi + 1) * N, a + hi + 1, K - (a + hi + 1)));
       }
+    }
   }
   R.ws.reset(mark);
 }
 
-void decompose(Run& R, int level, const uint64_t* x, uint64_t* digits) { decompose(R, level, IOList{{x, digits}}); }
-
 enum DivKind { DIV_MODDOWN, DIV_MODDOWN_RESCALE, DIV_RESCALE };
 
-// Division step of eq. (4) / eq. (1), for several inputs of the same kind:
+// Division step of eq. (4) / eq. (1):
 //  DIV_MODDOWN:         x [alpha+l+1] -> out [l+1], divide by P
 //  DIV_MODDOWN_RESCALE: x [alpha+l+1] -> out [l],   divide by P q_l
 //  DIV_RESCALE:         x [l+1]       -> out [l],   divide by q_l
-void divide(Run& R, DivKind kind, int level, const IOList& xs) {
+// INTT of the dividing limbs -> BConv onto the kept limbs -> NTT whose last
+// pass applies out = (kept - conv) * divisor^-1.
+void divide(Run& R, DivKind kind, const Jobs& xs) {
   const ckks_params* P = R.P;
   const int a = P->alpha;
   const size_t N = R.N, mark = R.ws.mark();
-  int plan_idx, ns, nout;
-  if (kind == DIV_MODDOWN) {
-    plan_idx = P->plan_moddown[level];
-    ns = a;
-    nout = level + 1;
-  } else if (kind == DIV_MODDOWN_RESCALE) {
-    plan_idx = P->plan_mdrescale[level];
-    ns = a + 1;
-    nout = level;
-  } else {
-    plan_idx = P->plan_rescale[level];
-    ns = 1;
-    nout = level;
-  }
+  const int ns = kind == DIV_MODDOWN ? a : (kind == DIV_MODDOWN_RESCALE ? a + 1 : 1);
   std::vector<uint64_t*> coef(xs.size());
   for (size_t t = 0; t < xs.size(); ++t) coef[t] = R.limbs(ns);
-  if (!R.dry && !R.err) {
-    const BConvPlan* plan = P->plan(plan_idx);
+  if (R.live()) {
+    auto plan_of = [&](int level) {
+      const int idx = kind == DIV_MODDOWN ? P->plan_moddown[level]
+                                          : (kind == DIV_MODDOWN_RESCALE ? P->plan_mdrescale[level]
+                                                                         : P->plan_rescale[level]);
+      return P->plan(idx);
+    };
+    auto nout_of = [&](int level) { return kind == DIV_MODDOWN ? level + 1 : level; };
     {
       NttBatch inv(R, false);
       for (size_t t = 0; t < xs.size(); ++t) {
-        const uint64_t* x = xs[t].first;
+        const uint64_t* x = xs[t].in;
+        const int level = xs[t].level;
         if (kind == DIV_RESCALE) {
           inv.add(range(x + (size_t)level * N, coef[t], a + level, 1));
         } else {
@@ -200,64 +203,83 @@ void divide(Run& R, DivKind kind, int level, const IOList& xs) {
     }
     {
       BConvBatch bc(R, ns);
-      for (size_t t = 0; t < xs.size(); ++t) bc.add(plan, nout, coef[t], xs[t].second, a);
+      for (size_t t = 0; t < xs.size(); ++t)
+        bc.add(plan_of(xs[t].level), nout_of(xs[t].level), coef[t], xs[t].out, a);
     }
-    NttBatch fwd(R, true, EPI_SUBMUL, plan);
+    NttBatch fwd(R, true, EPI_SUBMUL);
     for (size_t t = 0; t < xs.size(); ++t) {
-      const uint64_t* keep = kind == DIV_RESCALE ? xs[t].first : xs[t].first + (size_t)a * N;
-      fwd.add(range(xs[t].second, xs[t].second, a, nout, keep));
+      const int level = xs[t].level;
+      const BConvPlan* plan = plan_of(level);
+      const uint64_t* keep = kind == DIV_RESCALE ? xs[t].in : xs[t].in + (size_t)a * N;
+      fwd.add(range(xs[t].out, xs[t].out, a, nout_of(level), keep, nullptr, plan->sinv, plan->sinv_sh));
     }
   }
   R.ws.reset(mark);
 }
 
-void divide(Run& R, DivKind kind, int level, const uint64_t* x, uint64_t* out) {
-  divide(R, kind, level, IOList{{x, out}});
-}
+// ---- key switching --------------------------------------------------------------
 
-// Key-switch inner products of several digit sets with several keys, phi on
-// write (hoisting: each digit set and each key is read once per launch).
-struct KsDigit {
-  const uint64_t* digits;
-  const uint64_t* add;   // may be null
-  bool add_pscaled;
-};
-struct KsKey {
+// One hoisted key-switch product: out = phi(add + <d, key>), phi(<d, key>),
+// with phi given by the Galois element of -r (gal_inv).
+struct KsTask {
+  const uint64_t* digits;  // [beta_l][K_l][N]
+  int level;
+  const uint64_t* add;     // null, [K_l][N], or Q-basis [l+1][N] multiplied by P
+  bool pscaled;
   const uint64_t* key;
   uint32_t gal_inv;
+  uint64_t* oa;
+  uint64_t* ob;
 };
-// out[i][k] = {a, b} destination of digit set i with key k (nulls skip).
-void keyswitch(Run& R, int level, const std::vector<KsDigit>& dig, const std::vector<KsKey>& keys,
-               const std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>>& out, bool accumulate) {
-  if (R.dry || R.err || dig.empty() || keys.empty()) return;
+
+// Packs tasks into launches of at most kMaxKs distinct keys and kMaxDig
+// distinct digit sets, so each key (and each digit set) is read once per
+// launch; digit sets of different levels share the key reads (limb l of a
+// key is the same prime at every level).
+void keyswitch(Run& R, const std::vector<KsTask>& tasks) {
+  if (!R.live() || tasks.empty()) return;
   const ckks_params* P = R.P;
-  for (size_t i0 = 0; i0 < dig.size(); i0 += kMaxDig) {
-    for (size_t k0 = 0; k0 < keys.size(); k0 += kMaxKs) {
+  std::vector<const uint64_t*> keys;
+  for (const KsTask& t : tasks)
+    if (std::find(keys.begin(), keys.end(), t.key) == keys.end()) keys.push_back(t.key);
+  for (size_t k0 = 0; k0 < keys.size(); k0 += kMaxKs) {
+    const size_t k1 = std::min(keys.size(), k0 + kMaxKs);
+    std::vector<const uint64_t*> digs;  // digit sets used with this chunk of keys
+    for (const KsTask& t : tasks) {
+      const size_t ki = std::find(keys.begin(), keys.end(), t.key) - keys.begin();
+      if (ki < k0 || ki >= k1) continue;
+      if (std::find(digs.begin(), digs.end(), t.digits) == digs.end()) digs.push_back(t.digits);
+    }
+    for (size_t i0 = 0; i0 < digs.size(); i0 += kMaxDig) {
+      const size_t i1 = std::min(digs.size(), i0 + kMaxDig);
       KsArgs ka;
       memset(&ka, 0, sizeof(ka));
-      ka.beta = P->beta(level);
-      ka.K = P->K(level);
       ka.kmax = P->Kmax();
-      ka.accumulate = accumulate ? 1 : 0;
-      ka.ndig = (int)std::min(dig.size() - i0, (size_t)kMaxDig);
-      ka.nkeys = (int)std::min(keys.size() - k0, (size_t)kMaxKs);
-      for (int i = 0; i < ka.ndig; ++i) {
-        ka.digits[i] = dig[i0 + i].digits;
-        ka.add[i] = dig[i0 + i].add;
-        ka.add_pscaled[i] = dig[i0 + i].add_pscaled ? 1 : 0;
-        for (int k = 0; k < ka.nkeys; ++k) {
-          ka.out_a[i][k] = out[i0 + i][k0 + k].first;
-          ka.out_b[i][k] = out[i0 + i][k0 + k].second;
-        }
-      }
-      for (int k = 0; k < ka.nkeys; ++k) {
-        ka.key[k] = keys[k0 + k].key;
-        ka.gal_inv[k] = keys[k0 + k].gal_inv;
+      ka.nkeys = (int)(k1 - k0);
+      ka.ndig = (int)(i1 - i0);
+      for (size_t k = k0; k < k1; ++k) ka.key[k - k0] = keys[k];
+      for (const KsTask& t : tasks) {
+        const size_t ki = std::find(keys.begin(), keys.end(), t.key) - keys.begin();
+        const size_t di = std::find(digs.begin(), digs.end(), t.digits) - digs.begin();
+        if (ki < k0 || ki >= k1 || di < i0 || di >= i1) continue;
+        const int i = (int)(di - i0), k = (int)(ki - k0);
+        ka.digits[i] = t.digits;
+        ka.K[i] = P->K(t.level);
+        ka.beta[i] = P->beta(t.level);
+        ka.add[i] = t.add;
+        ka.add_pscaled[i] = t.pscaled ? 1 : 0;
+        ka.gal_inv[k] = t.gal_inv;
+        ka.out_a[i][k] = t.oa;
+        ka.out_b[i][k] = t.ob;
+        ka.kbeta = std::max(ka.kbeta, ka.beta[i]);
+        ka.maxK = std::max(ka.maxK, ka.K[i]);
       }
       R.check(launch_keyswitch(P, ka, R.s));
     }
   }
 }
+
+// ---- plaintext multiply-accumulate --------------------------------------------
 
 struct MacTerm {
   const uint64_t* a;
@@ -269,7 +291,7 @@ struct MacTerm {
 // outs[k] = sum_m terms[m] * f[k], over nlimbs limbs starting at prime_off.
 void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms, const std::vector<uint64_t*>& o0,
            const std::vector<uint64_t*>& o1) {
-  if (R.dry || R.err) return;
+  if (!R.live()) return;
   const int nk_all = (int)o0.size();
   for (int k0 = 0; k0 < nk_all; k0 += kMaxMacK) {
     const int nk = std::min(kMaxMacK, nk_all - k0);
@@ -307,12 +329,12 @@ void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms,
 
 void automorph(Run& R, int nlimbs, int prime_off, uint32_t gal, const uint64_t* in, const uint64_t* add,
                uint64_t* out, bool accumulate) {
-  if (R.dry || R.err) return;
+  if (!R.live()) return;
   AutoArgs aa{in, add, out, nlimbs, prime_off, accumulate ? 1 : 0, gal};
   R.check(launch_automorph(R.P, aa, R.s));
 }
 
-// ---- keys -------------------------------------------------------------------
+// ---- keys -----------------------------------------------------------------------
 
 struct KeySet {
   std::map<long, const uint64_t*> m;
@@ -329,8 +351,9 @@ struct KeySet {
 };
 
 // Rot(ct, r) = (phi_r(c0 + x), phi_r(y)), (x, y) = ModDown(<Decompose(c1), swk~_r>),
-// for several independent rotations at once (each with its own Decompose, as
-// plain BSGS and the diagonal method prescribe; only the launches are shared).
+// for several independent rotations at one level (each with its own
+// Decompose, as plain BSGS and the diagonal method prescribe; only the
+// launches are shared).
 struct RotJob {
   const uint64_t* c0;
   const uint64_t* c1;
@@ -347,10 +370,8 @@ void rotate(Run& R, int level, const std::vector<RotJob>& jobs, const KeySet& ks
     const size_t nj = std::min(jobs.size() - j0, (size_t)kMaxDig);
     const size_t mark = R.ws.mark();
     std::vector<uint64_t*> D(nj), X(nj), Y(nj), Xq(nj), Yq(nj);
-    IOList dc, md;
-    std::vector<KsDigit> dig;
-    std::vector<KsKey> keys;
-    std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>> out(nj);
+    Jobs dc, md;
+    std::vector<KsTask> tasks;
     for (size_t t = 0; t < nj; ++t) {
       D[t] = R.limbs((size_t)beta * K);
       X[t] = R.limbs(K);
@@ -360,17 +381,14 @@ void rotate(Run& R, int level, const std::vector<RotJob>& jobs, const KeySet& ks
     }
     for (size_t t = 0; t < nj; ++t) {
       const RotJob& J = jobs[j0 + t];
-      dc.push_back({J.c1, D[t]});
-      md.push_back({X[t], Xq[t]});
-      md.push_back({Y[t], Yq[t]});
-      dig.push_back(KsDigit{D[t], nullptr, false});
-      keys.push_back(KsKey{ks.get(R, J.r), 1u});
-      for (size_t u = 0; u < nj; ++u)
-        out[t].push_back(u == t ? std::make_pair(X[t], Y[t]) : std::make_pair((uint64_t*)nullptr, (uint64_t*)nullptr));
+      dc.push_back({level, J.c1, D[t]});
+      md.push_back({level, X[t], Xq[t]});
+      md.push_back({level, Y[t], Yq[t]});
+      tasks.push_back(KsTask{D[t], level, nullptr, false, ks.get(R, J.r), 1u, X[t], Y[t]});
     }
-    decompose(R, level, dc);
-    keyswitch(R, level, dig, keys, out, false);
-    divide(R, DIV_MODDOWN, level, md);
+    decompose(R, dc);
+    keyswitch(R, tasks);
+    divide(R, DIV_MODDOWN, md);
     for (size_t t = 0; t < nj; ++t) {
       const RotJob& J = jobs[j0 + t];
       const uint32_t g = galois(P, J.r);
@@ -387,164 +405,181 @@ struct Diag {
   bool has(int m) const { return m >= 0 && m < n && pt[m] != nullptr; }
 };
 
-// ---- triple-hoisted BSGS, Algorithm 2 ----------------------------------------
-void lt_th(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, int n3, const Diag& D,
-           const KeySet& ks, uint64_t* o0, uint64_t* o1) {
+// ---- triple-hoisted BSGS, Algorithm 2, for one or many ciphertexts ----------------
+
+struct ThItem {
+  int level;
+  const uint64_t* c0;
+  const uint64_t* c1;
+  int n1, n2, n3;
+  Diag D;
+  const KeySet* ks;
+  uint64_t* o0;
+  uint64_t* o1;
+  // which parts of the algorithm carry a present diagonal
+  std::vector<char> used_m, used_i, mid_i, used_k;
+  bool need_d0 = false;
+  // buffers
+  std::vector<uint64_t*> Dg, A, B, U0, U1, tmpQ, tmpK, Dk;
+};
+
+void lt_th(Run& R, std::vector<ThItem>& items) {
   const ckks_params* P = R.P;
-  const int K = P->K(level), beta = P->beta(level), inner = n1 * n2, Lq = level + 1;
-  const size_t N = R.N;
-  std::vector<char> used_m(inner, 0), used_i(n1, 0), mid_i(n1, 0), used_k(n3, 0);
-  for (int k = 0; k < n3; ++k)
+  // Plan every item and take its buffers.
+  for (ThItem& it : items) {
+    const int K = P->K(it.level), beta = P->beta(it.level), inner = it.n1 * it.n2, Lq = it.level + 1;
+    it.used_m.assign(inner, 0);
+    it.used_i.assign(it.n1, 0);
+    it.mid_i.assign(it.n1, 0);
+    it.used_k.assign(it.n3, 0);
+    for (int k = 0; k < it.n3; ++k)
+      for (int m = 0; m < inner; ++m)
+        if (it.D.has(k * inner + m)) it.used_m[m] = 1, it.used_k[k] = 1;
     for (int m = 0; m < inner; ++m)
-      if (D.has(k * inner + m)) used_m[m] = 1, used_k[k] = 1;
-  for (int m = 0; m < inner; ++m)
-    if (used_m[m]) {
-      used_i[m % n1] = 1;
-      if (m >= n1) mid_i[m % n1] = 1;
+      if (it.used_m[m]) {
+        it.used_i[m % it.n1] = 1;
+        if (m >= it.n1) it.mid_i[m % it.n1] = 1;
+      }
+    it.need_d0 = it.mid_i[0];
+    for (int i = 1; i < it.n1; ++i) it.need_d0 = it.need_d0 || it.used_i[i];
+    it.Dg.assign(it.n1, nullptr);
+    it.A.assign(inner, nullptr);
+    it.B.assign(inner, nullptr);
+    it.tmpQ.assign(it.n1, nullptr);
+    for (int i = 0; i < it.n1; ++i)
+      if ((i == 0 && it.need_d0) || (i > 0 && it.mid_i[i])) it.Dg[i] = R.limbs((size_t)beta * K);
+    for (int m = 1; m < inner; ++m)
+      if (it.used_m[m] || (m < it.n1 && it.used_i[m])) {
+        it.A[m] = R.limbs(K);
+        it.B[m] = R.limbs(K);
+      }
+    for (int i = 1; i < it.n1; ++i)
+      if (it.mid_i[i]) it.tmpQ[i] = R.limbs(Lq);
+    it.U0.assign(it.n3, nullptr);
+    it.U1.assign(it.n3, nullptr);
+    it.tmpK.assign(it.n3, nullptr);
+    it.Dk.assign(it.n3, nullptr);
+    for (int k = 0; k < it.n3; ++k) {
+      if (k > 0 && !it.used_k[k]) continue;
+      it.U0[k] = R.limbs(K);
+      it.U1[k] = R.limbs(K);
+      if (k > 0) {
+        it.tmpK[k] = R.limbs(Lq);
+        it.Dk[k] = R.limbs((size_t)beta * K);
+      }
     }
-  bool need_d0 = mid_i[0];
-  for (int i = 1; i < n1; ++i) need_d0 = need_d0 || used_i[i];
-
-  std::vector<uint64_t*> Dg(n1, nullptr), A(inner, nullptr), B(inner, nullptr);
-  for (int i = 0; i < n1; ++i)
-    if ((i == 0 && need_d0) || (i > 0 && mid_i[i])) Dg[i] = R.limbs((size_t)beta * K);
-  for (int m = 1; m < inner; ++m)
-    if (used_m[m] || (m < n1 && used_i[m])) {
-      A[m] = R.limbs(K);
-      B[m] = R.limbs(K);
-    }
-  std::vector<uint64_t*> U0(n3, nullptr), U1(n3, nullptr);
-  for (int k = 0; k < n3; ++k) {
-    U0[k] = R.limbs(K);
-    U1[k] = R.limbs(K);
   }
-  std::vector<uint64_t*> tmpQ(n1, nullptr), tmpK(n3, nullptr), Dk(n3, nullptr);
-  for (int i = 1; i < n1; ++i)
-    if (mid_i[i]) tmpQ[i] = R.limbs(Lq);
-  for (int k = 1; k < n3; ++k)
-    if (used_k[k]) {
-      tmpK[k] = R.limbs(Lq);
-      Dk[k] = R.limbs((size_t)beta * K);
-    }
-
   // Line 1: d_0 = Decompose(c1').
-  if (need_d0) decompose(R, level, c1, Dg[0]);
-  // Lines 3-5: inner rotations share d_0; a_0 = P c0' is applied inside the kernel.
   {
-    std::vector<KsKey> keys;
-    std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>> out(1);
-    for (int i = 1; i < n1; ++i) {
-      if (!used_i[i]) continue;
-      keys.push_back(KsKey{ks.get(R, i), galois(P, -i)});
-      out[0].push_back({A[i], B[i]});
-    }
-    keyswitch(R, level, {KsDigit{Dg[0], c0, true}}, keys, out, false);
+    Jobs dc;
+    for (ThItem& it : items)
+      if (it.need_d0) dc.push_back({it.level, it.c1, it.Dg[0]});
+    decompose(R, dc);
   }
-  // Lines 6-7: d_i = Decompose(ModDown(b_i)), all i at once (independent).
+  // Lines 2-5: inner rotations share d_0; a_0 = P c0' is applied inside the kernel.
   {
-    IOList md, dc;
-    for (int i = 1; i < n1; ++i) {
-      if (!mid_i[i]) continue;
-      md.push_back({B[i], tmpQ[i]});
-      dc.push_back({tmpQ[i], Dg[i]});
-    }
-    if (!md.empty()) {
-      divide(R, DIV_MODDOWN, level, md);
-      decompose(R, level, dc);
-    }
+    std::vector<KsTask> tasks;
+    for (ThItem& it : items)
+      for (int i = 1; i < it.n1; ++i)
+        if (it.used_i[i])
+          tasks.push_back(KsTask{it.Dg[0], it.level, it.c0, true, it.ks->get(R, i), galois(P, -i), it.A[i], it.B[i]});
+    keyswitch(R, tasks);
   }
-  // Lines 8-11: middle rotations by n1 j share d_i; one launch reads every
-  // middle key once for all digit sets d_0 .. d_{n1-1}.
+  // Lines 6-7: d_i = Decompose(ModDown(b_i)), every i at once.
   {
-    std::vector<KsDigit> dig;
-    std::vector<int> di;
-    for (int i = 0; i < n1; ++i)
-      if (mid_i[i]) {
-        dig.push_back(KsDigit{Dg[i], i == 0 ? c0 : A[i], i == 0});
-        di.push_back(i);
-      }
-    std::vector<KsKey> keys;
-    std::vector<int> kj;
-    for (int j = 1; j < n2; ++j) {
-      bool any = false;
-      for (int i : di) any = any || used_m[n1 * j + i];
-      if (!any) continue;
-      keys.push_back(KsKey{ks.get(R, (long)n1 * j), galois(P, -(long)n1 * j)});
-      kj.push_back(j);
-    }
-    std::vector<std::vector<std::pair<uint64_t*, uint64_t*>>> out(dig.size());
-    for (size_t x = 0; x < dig.size(); ++x)
-      for (int j : kj) {
-        const int m = n1 * j + di[x];
-        out[x].push_back(used_m[m] ? std::make_pair(A[m], B[m]) : std::make_pair((uint64_t*)nullptr, (uint64_t*)nullptr));
-      }
-    keyswitch(R, level, dig, keys, out, false);
+    Jobs md, dc;
+    for (ThItem& it : items)
+      for (int i = 1; i < it.n1; ++i)
+        if (it.mid_i[i]) {
+          md.push_back({it.level, it.B[i], it.tmpQ[i]});
+          dc.push_back({it.level, it.tmpQ[i], it.Dg[i]});
+        }
+    divide(R, DIV_MODDOWN, md);
+    decompose(R, dc);
   }
-  // Lines 12 and 14: all plaintext products at once.
+  // Lines 8-11: middle rotations by n1 j share d_i; each middle key is read
+  // once per launch for all digit sets.
   {
-    std::vector<MacTerm> terms;
-    std::vector<int> ks_out;
-    for (int k = 0; k < n3; ++k)
-      if (k == 0 || used_k[k]) ks_out.push_back(k);
-    for (int m = 0; m < inner; ++m) {
-      if (!used_m[m]) continue;
-      MacTerm t;
-      t.a = m == 0 ? c0 : A[m];
-      t.b = m == 0 ? c1 : B[m];
-      t.pscaled = (m == 0);
-      for (int k : ks_out) t.f.push_back(D.has(k * inner + m) ? D.pt[k * inner + m] : nullptr);
-      terms.push_back(t);
-    }
-    std::vector<uint64_t*> oo0, oo1;
-    for (int k : ks_out) {
-      oo0.push_back(U0[k]);
-      oo1.push_back(U1[k]);
-    }
-    if (terms.empty()) {
-      // No diagonal at all: the result is the encryption of zero.
-      MacTerm t{c0, c1, true, std::vector<const uint64_t*>(ks_out.size(), nullptr)};
-      terms.push_back(t);
-    }
-    ptmac(R, K, 0, terms, oo0, oo1);
+    std::vector<KsTask> tasks;
+    for (ThItem& it : items)
+      for (int j = 1; j < it.n2; ++j)
+        for (int i = 0; i < it.n1; ++i) {
+          const int m = it.n1 * j + i;
+          if (!it.mid_i[i] || !it.used_m[m]) continue;
+          const long r = (long)it.n1 * j;
+          tasks.push_back(KsTask{it.Dg[i], it.level, i == 0 ? it.c0 : it.A[i], i == 0, it.ks->get(R, r),
+                                 galois(P, -r), it.A[m], it.B[m]});
+        }
+    keyswitch(R, tasks);
   }
-  // Lines 13-18: outer rotations by n1 n2 k, all k at once: ModDown and
-  // Decompose batched, then one gather kernel adds phi_G(u0 + x), phi_G(y)
-  // of every k into (c0, c1).
-  {
-    IOList md, dc;
+  // Lines 12 and 14: all plaintext products of an item at once.
+  for (ThItem& it : items) {
+    const int K = P->K(it.level), inner = it.n1 * it.n2;
     std::vector<int> kk;
-    for (int k = 1; k < n3; ++k) {
-      if (!used_k[k]) continue;
-      md.push_back({U1[k], tmpK[k]});
-      dc.push_back({tmpK[k], Dk[k]});
-      kk.push_back(k);
+    for (int k = 0; k < it.n3; ++k)
+      if (k == 0 || it.used_k[k]) kk.push_back(k);
+    std::vector<MacTerm> terms;
+    for (int m = 0; m < inner; ++m) {
+      if (!it.used_m[m]) continue;
+      MacTerm t{m == 0 ? it.c0 : it.A[m], m == 0 ? it.c1 : it.B[m], m == 0, {}};
+      for (int k : kk) t.f.push_back(it.D.has(k * inner + m) ? it.D.pt[k * inner + m] : nullptr);
+      terms.push_back(t);
     }
-    if (!kk.empty()) {
-      divide(R, DIV_MODDOWN, level, md);
-      decompose(R, level, dc);
+    // No diagonal at all: the result is an encryption of zero.
+    if (terms.empty()) terms.push_back(MacTerm{it.c0, it.c1, true, std::vector<const uint64_t*>(kk.size(), nullptr)});
+    std::vector<uint64_t*> o0, o1;
+    for (int k : kk) {
+      o0.push_back(it.U0[k]);
+      o1.push_back(it.U1[k]);
+    }
+    ptmac(R, K, 0, terms, o0, o1);
+  }
+  // Lines 13-18: outer rotations by n1 n2 k: ModDown and Decompose of every
+  // (item, k) at once, then per item one gather kernel adds
+  // phi_G(u0 + x), phi_G(y) of all its k into (c0, c1).
+  {
+    Jobs md, dc;
+    for (ThItem& it : items)
+      for (int k = 1; k < it.n3; ++k)
+        if (it.used_k[k]) {
+          md.push_back({it.level, it.U1[k], it.tmpK[k]});
+          dc.push_back({it.level, it.tmpK[k], it.Dk[k]});
+        }
+    divide(R, DIV_MODDOWN, md);
+    decompose(R, dc);
+    for (ThItem& it : items) {
+      std::vector<int> kk;
+      for (int k = 1; k < it.n3; ++k)
+        if (it.used_k[k]) kk.push_back(k);
       for (size_t k0 = 0; k0 < kk.size(); k0 += kMaxKs) {
         KsGatherArgs ga;
         memset(&ga, 0, sizeof(ga));
-        ga.beta = beta;
-        ga.K = K;
+        ga.beta = P->beta(it.level);
+        ga.K = P->K(it.level);
         ga.kmax = P->Kmax();
-        ga.c0 = U0[0];
-        ga.c1 = U1[0];
+        ga.c0 = it.U0[0];
+        ga.c1 = it.U1[0];
         for (size_t t = k0; t < std::min(kk.size(), k0 + kMaxKs); ++t) {
-          const long G = (long)inner * kk[t];
-          ga.digits[ga.nk] = Dk[kk[t]];
-          ga.key[ga.nk] = ks.get(R, G);
-          ga.add[ga.nk] = U0[kk[t]];
+          const long G = (long)it.n1 * it.n2 * kk[t];
+          ga.digits[ga.nk] = it.Dk[kk[t]];
+          ga.key[ga.nk] = it.ks->get(R, G);
+          ga.add[ga.nk] = it.U0[kk[t]];
           ga.gal[ga.nk] = galois(P, G);
           ++ga.nk;
         }
-        if (!R.dry && !R.err) R.check(launch_keyswitch_gather(P, ga, R.s));
+        if (R.live()) R.check(launch_keyswitch_gather(P, ga, R.s));
       }
     }
   }
   // Line 19: ModDown by P q_l (ModDown and rescale combined).
-  divide(R, DIV_MODDOWN_RESCALE, level, IOList{{U0[0], o0}, {U1[0], o1}});
-  (void)N;
+  {
+    Jobs md;
+    for (ThItem& it : items) {
+      md.push_back({it.level, it.U0[0], it.o0});
+      md.push_back({it.level, it.U1[0], it.o1});
+    }
+    divide(R, DIV_MODDOWN_RESCALE, md);
+  }
 }
 
 // ---- plain BSGS, eq. (5) -------------------------------------------------------
@@ -606,7 +641,7 @@ void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
       if (used_j[j]) jobs.push_back(RotJob{S0[j], S1[j], (long)n1 * j, A0, A1, true});
     rotate(R, level, jobs, ks);
   }
-  divide(R, DIV_RESCALE, level, IOList{{A0, o0}, {A1, o1}});
+  divide(R, DIV_RESCALE, Jobs{{level, A0, o0}, {level, A1, o1}});
 }
 
 // ---- diagonal method ---------------------------------------------------------
@@ -632,54 +667,89 @@ void lt_naive(Run& R, int level, const uint64_t* c0, const uint64_t* c1, const D
   for (size_t t = 0; t < ds.size(); ++t) terms.push_back(MacTerm{T0[t], T1[t], false, {D.pt[ds[t]]}});
   if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, {nullptr}});
   ptmac(R, Lq, P->alpha, terms, {A0}, {A1});
-  divide(R, DIV_RESCALE, level, IOList{{A0, o0}, {A1, o1}});
+  divide(R, DIV_RESCALE, Jobs{{level, A0, o0}, {level, A1, o1}});
 }
 
-// ---- argument checks -----------------------------------------------------------
+// ---- argument checks -------------------------------------------------------------
 bool overlap(const void* a, size_t an, const void* b, size_t bn) {
   const uint8_t *x = (const uint8_t*)a, *y = (const uint8_t*)b;
   return x < y + bn && y < x + an;
 }
 
-int plan_lt(Run& R, const ckks_ct* in, const ckks_lt_diags* diags, const ckks_rotkeys* keys, int algo,
-            ckks_ct* out) {
-  const ckks_params* P = R.P;
-  if (!in || !diags || !out || !in->c0 || !in->c1 || !out->c0 || !out->c1) return CKKS_E_INVALID_ARG;
+// Validates one LT's arguments (no device access); fills ks from keys.
+int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* diags, const ckks_rotkeys* keys,
+               int algo, const ckks_ct* out, bool check_buffers, KeySet* ks) {
+  if (!in || !diags || !out) return CKKS_E_INVALID_ARG;
   const int level = in->level;
   if (level < 1 || level > P->L) return CKKS_E_INVALID_ARG;
   if (diags->n_diag < 0 || (diags->n_diag > 0 && !diags->pt)) return CKKS_E_INVALID_ARG;
-  const size_t in_bytes = (size_t)(level + 1) * R.N * 8, out_bytes = (size_t)level * R.N * 8;
-  for (const void* o : {(const void*)out->c0, (const void*)out->c1})
-    for (const void* i : {(const void*)in->c0, (const void*)in->c1})
-      if (overlap(o, out_bytes, i, in_bytes)) return CKKS_E_INVALID_ARG;
-  if (overlap(out->c0, out_bytes, out->c1, out_bytes)) return CKKS_E_INVALID_ARG;
-  KeySet ks;
-  ks.S = P->n / 2;
+  if (check_buffers) {
+    if (!in->c0 || !in->c1 || !out->c0 || !out->c1) return CKKS_E_INVALID_ARG;
+    const size_t N = (size_t)P->n;
+    const size_t in_bytes = (size_t)(level + 1) * N * 8, out_bytes = (size_t)level * N * 8;
+    for (const void* o : {(const void*)out->c0, (const void*)out->c1})
+      for (const void* i : {(const void*)in->c0, (const void*)in->c1})
+        if (overlap(o, out_bytes, i, in_bytes)) return CKKS_E_INVALID_ARG;
+    if (overlap(out->c0, out_bytes, out->c1, out_bytes)) return CKKS_E_INVALID_ARG;
+  }
+  ks->S = P->n / 2;
   if (keys) {
     if (keys->count < 0 || (keys->count > 0 && (!keys->rot || !keys->key))) return CKKS_E_INVALID_ARG;
-    for (int i = 0; i < keys->count; ++i) ks.m[((keys->rot[i] % ks.S) + ks.S) % ks.S] = keys->key[i];
+    for (int i = 0; i < keys->count; ++i) ks->m[((keys->rot[i] % ks->S) + ks->S) % ks->S] = keys->key[i];
   }
-  Diag D;
-  D.n = diags->n_diag;
-  D.pt = diags->pt;
-  R.N = (size_t)P->n;
-  R.ws.limb_bytes = R.N * 8;
   if (algo == CKKS_LT_TH_BSGS) {
     const int n1 = diags->n1, n2 = diags->n2, n3 = diags->n3;
-    if (n1 < 1 || n2 < 1 || n3 < 1 || (long)n1 * n2 * n3 < diags->n_diag || n1 * n2 > 4096) return CKKS_E_INVALID_ARG;
-    // exact 128-bit accumulation over one MAC chunk: kMaxMacM q^2 < 2^128 (q < 2^61)
-    lt_th(R, level, in->c0, in->c1, n1, n2, n3, D, ks, out->c0, out->c1);
-  } else if (algo == CKKS_LT_BSGS) {
+    if (n1 < 1 || n2 < 1 || n3 < 1 || (long)n1 * n2 * n3 < diags->n_diag || (long)n1 * n2 * n3 > P->n / 2)
+      return CKKS_E_INVALID_ARG;
+  } else if (algo == CKKS_LT_BSGS || algo == CKKS_LT_DH_BSGS) {
     const int n1 = diags->n1, n2 = diags->n2;
-    if (n1 < 1 || n2 < 1 || (long)n1 * n2 < diags->n_diag) return CKKS_E_INVALID_ARG;
-    lt_bsgs(R, level, in->c0, in->c1, n1, n2, D, ks, out->c0, out->c1);
+    if (n1 < 1 || n2 < 1 || (long)n1 * n2 < diags->n_diag || (long)n1 * n2 > P->n / 2) return CKKS_E_INVALID_ARG;
   } else if (algo == CKKS_LT_NAIVE) {
     if (diags->n_diag > P->n / 2) return CKKS_E_INVALID_ARG;
-    lt_naive(R, level, in->c0, in->c1, D, ks, out->c0, out->c1);
   } else {
     return CKKS_E_INVALID_ARG;
   }
-  return R.err;
+  return CKKS_OK;
+}
+
+// DH-BSGS (Algorithm 1) with n1 baby and n2 giant steps is Algorithm 2 with
+// an empty inner layer: (n1', n2', n3') = (1, n1, n2).
+ThItem th_item(const ckks_ct* in, const ckks_lt_diags* d, const KeySet* ks, ckks_ct* out, bool dh) {
+  ThItem it;
+  it.level = in->level;
+  it.c0 = in->c0;
+  it.c1 = in->c1;
+  it.n1 = dh ? 1 : d->n1;
+  it.n2 = dh ? d->n1 : d->n2;
+  it.n3 = dh ? d->n2 : d->n3;
+  it.D.n = d->n_diag;
+  it.D.pt = d->pt;
+  it.ks = ks;
+  it.o0 = out->c0;
+  it.o1 = out->c1;
+  return it;
+}
+
+// Runs (or, dry, plans) LTs of one algorithm.  TH-BSGS items run in lockstep;
+// the other algorithms run one item after the other.
+void run_items(Run& R, int algo, const std::vector<const ckks_ct*>& in, const std::vector<const ckks_lt_diags*>& dg,
+               const std::vector<KeySet>& ks, const std::vector<ckks_ct*>& out) {
+  if (algo == CKKS_LT_TH_BSGS || algo == CKKS_LT_DH_BSGS) {
+    std::vector<ThItem> items;
+    for (size_t t = 0; t < in.size(); ++t)
+      items.push_back(th_item(in[t], dg[t], &ks[t], out[t], algo == CKKS_LT_DH_BSGS));
+    lt_th(R, items);
+    return;
+  }
+  for (size_t t = 0; t < in.size(); ++t) {
+    Diag D;
+    D.n = dg[t]->n_diag;
+    D.pt = dg[t]->pt;
+    if (algo == CKKS_LT_BSGS)
+      lt_bsgs(R, in[t]->level, in[t]->c0, in[t]->c1, dg[t]->n1, dg[t]->n2, D, ks[t], out[t]->c0, out[t]->c1);
+    else
+      lt_naive(R, in[t]->level, in[t]->c0, in[t]->c1, D, ks[t], out[t]->c0, out[t]->c1);
+  }
 }
 
 struct DeviceGuard {
@@ -691,6 +761,33 @@ struct DeviceGuard {
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
+
+Run make_run(const ckks_params* P, void* stream, bool dry, void* ws) {
+  Run R;
+  R.P = P;
+  R.s = (hipStream_t)stream;
+  R.N = (size_t)P->n;
+  R.dry = dry;
+  R.ws.base = (uint8_t*)ws;
+  R.ws.limb_bytes = R.N * 8;
+  return R;
+}
+
+// Plans (dry) then runs a list of items; *need receives the workspace bytes.
+int eval_items(const ckks_params* P, int algo, const std::vector<const ckks_ct*>& in,
+               const std::vector<const ckks_lt_diags*>& dg, const std::vector<KeySet>& ks,
+               const std::vector<ckks_ct*>& out, void* ws, size_t ws_bytes, void* stream, bool plan_only,
+               size_t* need) {
+  Run D = make_run(P, stream, true, nullptr);
+  run_items(D, algo, in, dg, ks, out);
+  if (need) *need = D.ws.peak;
+  if (plan_only) return CKKS_OK;
+  if (D.err != CKKS_OK) return D.err;
+  if (D.ws.peak > ws_bytes || (D.ws.peak > 0 && !ws)) return CKKS_E_WORKSPACE;
+  Run X = make_run(P, stream, false, ws);
+  run_items(X, algo, in, dg, ks, out);
+  return X.err;
+}
 
 }  // namespace
 }  // namespace ckks
@@ -734,33 +831,13 @@ void ckks_params_info(const ckks_params* P, int* log_n, int* n_q, int* n_p) {
 int ckks_lt_workspace_size(const ckks_params* P, int level, const ckks_lt_diags* diags, int algo, size_t* bytes) {
   if (!P || !diags || !bytes) return CKKS_E_INVALID_ARG;
   try {
-    Run R;
-    R.P = P;
-    R.dry = true;
-    R.N = (size_t)P->n;
-    // sizes do not depend on the buffers: plan with placeholder pointers
-    static uint64_t dummy[2];
-    ckks_ct in{level, 1.0, dummy, dummy + 1}, out{level - 1, 1.0, dummy, dummy + 1};
-    // placeholder ciphertexts alias by construction; size the plan directly
-    R.ws.limb_bytes = R.N * 8;
-    KeySet ks;
-    ks.S = P->n / 2;
-    Diag D{diags->n_diag, diags->pt};
-    if (level < 1 || level > P->L) return CKKS_E_INVALID_ARG;
-    R.err = CKKS_OK;
-    if (algo == CKKS_LT_TH_BSGS) {
-      if (diags->n1 < 1 || diags->n2 < 1 || diags->n3 < 1) return CKKS_E_INVALID_ARG;
-      lt_th(R, level, in.c0, in.c1, diags->n1, diags->n2, diags->n3, D, ks, out.c0, out.c1);
-    } else if (algo == CKKS_LT_BSGS) {
-      if (diags->n1 < 1 || diags->n2 < 1) return CKKS_E_INVALID_ARG;
-      lt_bsgs(R, level, in.c0, in.c1, diags->n1, diags->n2, D, ks, out.c0, out.c1);
-    } else if (algo == CKKS_LT_NAIVE) {
-      lt_naive(R, level, in.c0, in.c1, D, ks, out.c0, out.c1);
-    } else {
-      return CKKS_E_INVALID_ARG;
-    }
-    *bytes = R.ws.peak;
-    return CKKS_OK;
+    // Sizes depend only on shapes: plan with placeholder buffers and no keys.
+    static uint64_t dummy[4];
+    ckks_ct in{level, 1.0, dummy, dummy + 1}, out{level - 1, 1.0, dummy + 2, dummy + 3};
+    std::vector<KeySet> ks(1);
+    int e = check_item(P, &in, diags, nullptr, algo, &out, false, &ks[0]);
+    if (e != CKKS_OK) return e;
+    return eval_items(P, algo, {&in}, {diags}, ks, {&out}, nullptr, 0, nullptr, true, bytes);
   } catch (...) {
     return CKKS_E_NOMEM;
   }
@@ -771,21 +848,10 @@ int ckks_lt_eval(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* d
   if (!P) return CKKS_E_INVALID_ARG;
   try {
     DeviceGuard dg(P->device);
-    Run R;
-    R.P = P;
-    R.s = (hipStream_t)stream;
-    R.N = (size_t)P->n;
-    R.dry = true;
-    int e = plan_lt(R, in, diags, keys, algo, out);
+    std::vector<KeySet> ks(1);
+    int e = check_item(P, in, diags, keys, algo, out, true, &ks[0]);
     if (e != CKKS_OK) return e;
-    if (R.ws.peak > ws_bytes || (R.ws.peak > 0 && !ws)) return CKKS_E_WORKSPACE;
-    Run X;
-    X.P = P;
-    X.s = R.s;
-    X.N = R.N;
-    X.dry = false;
-    X.ws.base = (uint8_t*)ws;
-    e = plan_lt(X, in, diags, keys, algo, out);
+    e = eval_items(P, algo, {in}, {diags}, ks, {out}, ws, ws_bytes, stream, false, nullptr);
     if (e != CKKS_OK) return e;
     out->level = in->level - 1;
     out->scale = in->scale * diags->pt_scale / (double)P->primes[P->alpha + in->level];
@@ -795,9 +861,94 @@ int ckks_lt_eval(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* d
   }
 }
 
+static int batch_common(const ckks_params* P, int count, ckks_lt_item* items, int algo, void* ws, size_t ws_bytes,
+                        void* stream, bool plan_only, size_t* need) {
+  if (!P || count < 0 || (count > 0 && !items)) return CKKS_E_INVALID_ARG;
+  std::vector<const ckks_ct*> in;
+  std::vector<const ckks_lt_diags*> dg;
+  std::vector<ckks_ct*> out;
+  std::vector<KeySet> ks;
+  std::vector<int> idx;
+  ks.reserve(count);
+  int first_err = CKKS_OK;
+  for (int t = 0; t < count; ++t) {
+    KeySet k;
+    const int e =
+        check_item(P, &items[t].in, &items[t].diags, items[t].keys, algo, &items[t].out, !plan_only, &k);
+    items[t].status = e;
+    if (e != CKKS_OK) {
+      if (first_err == CKKS_OK) first_err = e;
+      continue;
+    }
+    ks.push_back(k);
+    in.push_back(&items[t].in);
+    dg.push_back(&items[t].diags);
+    out.push_back(&items[t].out);
+    idx.push_back(t);
+  }
+  // an output must not overlap any input or another item's output
+  if (!plan_only) {
+    const size_t N = (size_t)P->n;
+    for (size_t a = 0; a < out.size(); ++a) {
+      const size_t ob = (size_t)in[a]->level * N * 8;
+      for (size_t b = 0; b < in.size(); ++b) {
+        const size_t ib = (size_t)(in[b]->level + 1) * N * 8, obb = (size_t)in[b]->level * N * 8;
+        for (const void* o : {(const void*)out[a]->c0, (const void*)out[a]->c1}) {
+          if (overlap(o, ob, in[b]->c0, ib) || overlap(o, ob, in[b]->c1, ib)) return CKKS_E_INVALID_ARG;
+          if (a != b && (overlap(o, ob, out[b]->c0, obb) || overlap(o, ob, out[b]->c1, obb)))
+            return CKKS_E_INVALID_ARG;
+        }
+      }
+    }
+  }
+  if (in.empty()) {
+    if (need) *need = 0;
+    return first_err;
+  }
+  const int e = eval_items(P, algo, in, dg, ks, out, ws, ws_bytes, stream, plan_only, need);
+  if (plan_only) return e;
+  for (size_t t = 0; t < idx.size(); ++t) {
+    ckks_lt_item& it = items[idx[t]];
+    it.status = e;
+    if (e == CKKS_OK) {
+      it.out.level = it.in.level - 1;
+      it.out.scale = it.in.scale * it.diags.pt_scale / (double)P->primes[P->alpha + it.in.level];
+    }
+  }
+  return e != CKKS_OK ? e : first_err;
+}
+
+int ckks_lt_batch_workspace_size(const ckks_params* P, int count, const ckks_lt_item* items, int algo,
+                                 size_t* bytes) {
+  if (!bytes || count < 0 || (count > 0 && !items)) return CKKS_E_INVALID_ARG;
+  try {
+    std::vector<ckks_lt_item> copy(items, items + count);
+    static uint64_t dummy[4];
+    for (auto& it : copy) {
+      it.in.c0 = it.in.c1 = dummy;
+      it.out.c0 = it.out.c1 = dummy + 2;
+      it.keys = nullptr;
+    }
+    return batch_common(P, count, copy.data(), algo, nullptr, 0, nullptr, true, bytes);
+  } catch (...) {
+    return CKKS_E_NOMEM;
+  }
+}
+
+int ckks_lt_eval_batch(const ckks_params* P, int count, ckks_lt_item* items, int algo, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (!P) return CKKS_E_INVALID_ARG;
+  try {
+    DeviceGuard dg(P->device);
+    return batch_common(P, count, items, algo, ws, ws_bytes, stream, false, nullptr);
+  } catch (...) {
+    return CKKS_E_NOMEM;
+  }
+}
+
 int ckks_op_workspace_size(const ckks_params* P, int level, size_t* bytes) {
   if (!P || !bytes || level < 0 || level > P->L) return CKKS_E_INVALID_ARG;
-  // decompose: Lq limbs; division: alpha + 1 limbs
+  // decompose: l+1 limbs; division: alpha + 1 limbs
   const size_t limb = (size_t)P->n * 8;
   *bytes = (size_t)std::max(level + 1, P->alpha + 1) * limb + 256;
   return CKKS_OK;
@@ -808,12 +959,7 @@ static int op_prologue(const ckks_params* P, int level, void* ws, size_t ws_byte
   size_t need = 0;
   ckks_op_workspace_size(P, level, &need);
   if (ws_bytes < need || !ws) return CKKS_E_WORKSPACE;
-  R.P = P;
-  R.s = (hipStream_t)stream;
-  R.N = (size_t)P->n;
-  R.dry = false;
-  R.ws.base = (uint8_t*)ws;
-  R.ws.limb_bytes = R.N * 8;
+  R = make_run(P, stream, false, ws);
   return CKKS_OK;
 }
 
@@ -822,12 +968,11 @@ int ckks_op_ntt(const ckks_params* P, int forward, int first_prime, int n_limbs,
   if (!P || !in || !out || n_limbs < 0 || first_prime < 0 || first_prime + n_limbs > P->Kmax())
     return CKKS_E_INVALID_ARG;
   DeviceGuard dg(P->device);
-  Run R;
-  R.P = P;
-  R.s = (hipStream_t)stream;
-  R.N = (size_t)P->n;
-  R.dry = false;
-  ntt_range(R, forward != 0, first_prime, n_limbs, in, out);
+  Run R = make_run(P, stream, false, nullptr);
+  {
+    NttBatch b(R, forward != 0);
+    b.add(range(in, out, first_prime, n_limbs));
+  }
   return R.err;
 }
 
@@ -838,7 +983,7 @@ int ckks_op_decompose(const ckks_params* P, int level, const uint64_t* x, uint64
   int e = op_prologue(P, level, ws, ws_bytes, R, stream);
   if (e) return e;
   DeviceGuard dg(P->device);
-  decompose(R, level, x, digits);
+  decompose(R, Jobs{{level, x, digits}});
   return R.err;
 }
 
@@ -849,7 +994,7 @@ int ckks_op_moddown(const ckks_params* P, int level, int rescale, const uint64_t
   int e = op_prologue(P, level, ws, ws_bytes, R, stream);
   if (e) return e;
   DeviceGuard dg(P->device);
-  divide(R, rescale ? DIV_MODDOWN_RESCALE : DIV_MODDOWN, level, x, out);
+  divide(R, rescale ? DIV_MODDOWN_RESCALE : DIV_MODDOWN, Jobs{{level, x, out}});
   return R.err;
 }
 
@@ -860,7 +1005,7 @@ int ckks_op_rescale(const ckks_params* P, int level, const uint64_t* x, uint64_t
   int e = op_prologue(P, level, ws, ws_bytes, R, stream);
   if (e) return e;
   DeviceGuard dg(P->device);
-  divide(R, DIV_RESCALE, level, x, out);
+  divide(R, DIV_RESCALE, Jobs{{level, x, out}});
   return R.err;
 }
 
@@ -868,13 +1013,8 @@ int ckks_op_keyswitch(const ckks_params* P, int level, const uint64_t* digits, c
                       const uint64_t* add, uint64_t* out_a, uint64_t* out_b, void* stream) {
   if (!P || !digits || !key || !out_a || !out_b || level < 0 || level > P->L) return CKKS_E_INVALID_ARG;
   DeviceGuard dg(P->device);
-  Run R;
-  R.P = P;
-  R.s = (hipStream_t)stream;
-  R.N = (size_t)P->n;
-  R.dry = false;
-  keyswitch(R, level, {KsDigit{digits, add, false}}, {KsKey{key, galois(P, -(long)rot)}}, {{{out_a, out_b}}},
-            false);
+  Run R = make_run(P, stream, false, nullptr);
+  keyswitch(R, {KsTask{digits, level, add, false, key, galois(P, -(long)rot), out_a, out_b}});
   return R.err;
 }
 
@@ -882,11 +1022,7 @@ int ckks_op_automorph(const ckks_params* P, int32_t rot, int n_limbs, const uint
                       void* stream) {
   if (!P || !in || !out || n_limbs < 0 || n_limbs > P->Kmax() || in == out) return CKKS_E_INVALID_ARG;
   DeviceGuard dg(P->device);
-  Run R;
-  R.P = P;
-  R.s = (hipStream_t)stream;
-  R.N = (size_t)P->n;
-  R.dry = false;
+  Run R = make_run(P, stream, false, nullptr);
   automorph(R, n_limbs, 0, galois(P, rot), in, nullptr, out, false);
   return R.err;
 }

@@ -20,9 +20,9 @@
 // in registers again.
 //
 // Two arithmetic paths, chosen per limb (uniform over a workgroup):
-//  * integer (q >= 2^48): Harvey's lazy butterflies ([0, 4q) forward,
+//  * integer (q >= 2^46): Harvey's lazy butterflies ([0, 4q) forward,
 //    [0, 2q) inverse) with Shoup twiddle products;
-//  * FP64 (q < 2^48): residues are doubles holding exact integers, the
+//  * FP64 (q < 2^46): residues are doubles holding exact integers, the
 //    twiddle product is the exact FMA two-product remainder of modarith.hpp,
 //    values are re-centred every 4 stages.  Between the two passes such a limb
 //    is stored as raw double bits; the final pass writes canonical residues.
@@ -44,7 +44,7 @@ __device__ __forceinline__ uint64_t as_u(double d) { return (uint64_t)__double_a
 
 template <int PLOG, int G, bool COL, bool FWD, bool FP>
 __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const PrimeDev& pr, int log_n, int epi,
-                                         const BConvPlan* __restrict__ plan, uint64_t* lds) {
+                                         uint64_t* lds) {
   constexpr int P = 1 << PLOG;
   constexpr int T = P / 16;           // threads per sub-transform
   constexpr int RS = P + P / 16 + 1;  // LDS row stride (padded)
@@ -175,8 +175,8 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
       const uint64_t* aux = (epi == EPI_SUBMUL) ? R.aux + (size_t)limb * n : nullptr;
       uint64_t c = 0, cs = 0;
       if (epi == EPI_SUBMUL) {
-        c = plan->sinv[R.epi0 + limb];
-        cs = plan->sinv_sh[R.epi0 + limb];
+        c = R.sinv[limb];
+        cs = R.sinv_sh[limb];
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -231,8 +231,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
 
 template <int PLOG, int G, bool COL, bool FWD>
 __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
-    ntt_pass(NttArgs args, const PrimeDev* __restrict__ primes, int log_n, int epi,
-             const BConvPlan* __restrict__ plan) {
+    ntt_pass(NttArgs args, const PrimeDev* __restrict__ primes, int log_n, int epi) {
   constexpr int P = 1 << PLOG;
   constexpr int RS = P + P / 16 + 1;
   __shared__ uint64_t lds[G * RS];
@@ -246,14 +245,13 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
   const LimbRange& R = args.r[ri];
   const PrimeDev& pr = primes[R.prime0 + limb];
   if (pr.fp)
-    ntt_body<PLOG, G, COL, FWD, true>(R, limb, pr, log_n, epi, plan, lds);
+    ntt_body<PLOG, G, COL, FWD, true>(R, limb, pr, log_n, epi, lds);
   else
-    ntt_body<PLOG, G, COL, FWD, false>(R, limb, pr, log_n, epi, plan, lds);
+    ntt_body<PLOG, G, COL, FWD, false>(R, limb, pr, log_n, epi, lds);
 }
 
 template <int PLOG, bool COL, bool FWD>
-hipError_t launch_pass(const ckks_params* P, const NttArgs& a, int total, int epi, const BConvPlan* plan,
-                       hipStream_t s) {
+hipError_t launch_pass(const ckks_params* P, const NttArgs& a, int total, int epi, hipStream_t s) {
   constexpr int Pn = 1 << PLOG;
   constexpr int G = 4096 / Pn;
   const int n = P->n;
@@ -267,35 +265,34 @@ hipError_t launch_pass(const ckks_params* P, const NttArgs& a, int total, int ep
     for (int i = 0; i < a.nr; ++i) words += a.r[i].copy ? (double)a.r[i].count * n : 0;
   ProfScope prof(id, s, words * 8);
   hipLaunchKernelGGL((ntt_pass<PLOG, G, COL, FWD>), grid, dim3(G * Pn / 16), 0, s, a, P->d_primes, P->log_n,
-                     epi, plan);
+                     epi);
   return hipGetLastError();
 }
 
 template <int PA, int PB>
-hipError_t launch_both(const ckks_params* P, bool forward, const NttArgs& a, int total, int epi,
-                       const BConvPlan* plan, hipStream_t s) {
+hipError_t launch_both(const ckks_params* P, bool forward, const NttArgs& a, int total, int epi, hipStream_t s) {
   hipError_t e;
   if (forward) {
-    e = launch_pass<PA, true, true>(P, a, total, EPI_NONE, nullptr, s);
+    e = launch_pass<PA, true, true>(P, a, total, EPI_NONE, s);
     if (e != hipSuccess) return e;
-    return launch_pass<PB, false, true>(P, a, total, epi, plan, s);
+    return launch_pass<PB, false, true>(P, a, total, epi, s);
   }
-  e = launch_pass<PB, false, false>(P, a, total, EPI_NONE, nullptr, s);
+  e = launch_pass<PB, false, false>(P, a, total, EPI_NONE, s);
   if (e != hipSuccess) return e;
-  return launch_pass<PA, true, false>(P, a, total, EPI_NONE, nullptr, s);
+  return launch_pass<PA, true, false>(P, a, total, EPI_NONE, s);
 }
 
 }  // namespace
 
 hipError_t launch_ntt(const ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
-                      const BConvPlan* epi_plan, hipStream_t s) {
+                      hipStream_t s) {
   if (total_limbs <= 0) return hipSuccess;
   switch (P->log_n) {
-    case 12: return launch_both<6, 6>(P, forward, a, total_limbs, epi, epi_plan, s);
-    case 13: return launch_both<7, 6>(P, forward, a, total_limbs, epi, epi_plan, s);
-    case 14: return launch_both<7, 7>(P, forward, a, total_limbs, epi, epi_plan, s);
-    case 15: return launch_both<8, 7>(P, forward, a, total_limbs, epi, epi_plan, s);
-    case 16: return launch_both<8, 8>(P, forward, a, total_limbs, epi, epi_plan, s);
+    case 12: return launch_both<6, 6>(P, forward, a, total_limbs, epi, s);
+    case 13: return launch_both<7, 6>(P, forward, a, total_limbs, epi, s);
+    case 14: return launch_both<7, 7>(P, forward, a, total_limbs, epi, s);
+    case 15: return launch_both<8, 7>(P, forward, a, total_limbs, epi, s);
+    case 16: return launch_both<8, 8>(P, forward, a, total_limbs, epi, s);
     default: return hipErrorInvalidValue;
   }
 }

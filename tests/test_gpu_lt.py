@@ -79,3 +79,28 @@ def test_lt_errors(toy):
         H.ckks_lt_eval(P, w.level, toy.delta, d["ct"][0], d["ct"][1], (2, 2, 2), pts, toy.delta, d["keys"],
                        H.CKKS_LT_TH_BSGS, o0, o1, ws, ws_bytes)
     assert e.value.code == H.CKKS_E_INVALID_ARG
+
+
+def test_dh_bsgs_is_th_with_unit_inner_layer(toy):
+    # CKKS_LT_DH_BSGS (n1, n2) == Algorithm 2 with (1, n1, n2), bit for bit.
+    import torch
+    w = toy.w
+    o = toy.o
+    split = (4, 4)
+    pts = o.th_plaintexts(w.diags, 1, *split, toy.delta)
+    keys = {r: k for r, k in toy.keys.items()}
+    need = set(W.th_rotations(1, *split))
+    for r in need - set(keys):
+        keys[r] = o.rotkey(r)
+    ref = o.lt_th(w.level, toy.ct, (1,) + split, pts, keys)
+    P = gpu_params(w.params)
+    d = toy.device()
+    dpts = [None if f is None else H.to_device(f) for f in pts]
+    dkeys = {r: H.to_device(k) for r, k in keys.items()}
+    wsb = H.ckks_lt_workspace_size(P, w.level, split, dpts, H.CKKS_LT_DH_BSGS)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    o0, o1 = H.empty((w.level, w.params.n)), H.empty((w.level, w.params.n))
+    H.ckks_lt_eval(P, w.level, toy.delta, d["ct"][0], d["ct"][1], split, dpts, toy.delta, dkeys,
+                   H.CKKS_LT_DH_BSGS, o0, o1, ws, wsb)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.stack([H.to_host(o0), H.to_host(o1)]), ref)

@@ -131,3 +131,16 @@ def test_th_multi_digit_groups():
     sc = delta * delta / prm.q[4]
     assert np.abs(o.decrypt_slots(th, sc) - ref).max() <= 5e-3
     assert np.abs(o.decrypt_slots(bs, sc) - ref).max() <= 5e-3
+
+
+@pytest.mark.parametrize("split", [(4, 4), (8, 2), (2, 8)])
+def test_dh_counts_table1(toy, split):
+    # Algorithm 1 (DH-BSGS) is Algorithm 2 with n1' = 1: Table I's DH row,
+    # n2 Decompose, n2 + 1 ModDown, n1 + n2 - 2 keys.
+    w, o, ct, keys, delta = toy
+    n1, n2 = split
+    o.reset_counters()
+    out = o.lt_th(w.level, ct, (1, n1, n2), o.th_plaintexts(w.diags, 1, n1, n2, delta), keys)
+    c = o.counters()
+    assert c["decompose"] == n2 and c["moddown"] == n2 + 1 and c["keys"] == n1 + n2 - 2
+    assert np.abs(_decode(o, out, w, delta) - W.matvec(w.diags, w.vector)).max() <= 5e-3
