@@ -44,6 +44,12 @@ extern "C" {
 #define CKKS_E_WORKSPACE -3    /* workspace smaller than ckks_*_workspace_size */
 #define CKKS_E_DEVICE -4       /* a HIP runtime call failed                   */
 #define CKKS_E_NOMEM -5        /* device allocation failed                    */
+#define CKKS_E_TIMEOUT -6      /* server: request waited past its queue limit */
+#define CKKS_E_CANCELLED -7    /* server: request cancelled before it started */
+
+/* Server request states that are not yet a result (see ckks_server_poll). */
+#define CKKS_PENDING 1         /* queued, not yet admitted                    */
+#define CKKS_RUNNING 2         /* admitted; its batch is on the device        */
 
 /* Text for an error code (static storage). */
 const char* ckks_strerror(int code);
@@ -91,19 +97,29 @@ typedef struct {
 
 /*
  * The diagonals of the LT matrix as NTT-form plaintexts (Section II-B).
- * Diagonal index m = n1 n2 k + n1 j + i (TH-BSGS) or n1 j + i (BSGS) or the
- * offset itself (diagonal method).  Plaintext m must already carry the
- * giant-step pre-rotation of Algorithm 2's input list:
- *   TH-BSGS : f^_m = phi_{-n1 n2 k}(f_m), PQ basis [alpha + L + 1][N]
- *   BSGS    : f^_m = phi_{-n1 j}(f_m),    Q basis  [L + 1][N]
- *   naive   : f_m,                        Q basis  [L + 1][N]
- * A NULL pointer is an all-zero diagonal and is skipped exactly.
+ * Index t = n1 n2 k + n1 j + i (TH-BSGS), n1 j + i (BSGS) or t (diagonal
+ * method) holds the cyclic diagonal at offset s (t - c) mod N/2, with
+ * s = stride and c = centre: plain Algorithm 2 is s = 1, c = 0 (offset t);
+ * other values serve sparse matrices whose diagonals form an arithmetic
+ * progression, negative offsets included (e.g. the factors of a DFT).  The
+ * rotations are s i (baby / inner), s n1 j (middle) and the giant step
+ * G_k = s (B k - c), B = n1 n2 (TH-BSGS) or n1 (BSGS); a block whose G_k is
+ * 0 mod N/2 is added without rotation (Algorithm 2's k = 0 block).
+ * Plaintext t must already carry its block's giant-step pre-rotation:
+ *   TH-BSGS : f^_t = phi_{-G_k}(f_t), PQ basis [alpha + L + 1][N]
+ *   BSGS    : f^_t = phi_{-G_j}(f_t), Q basis  [L + 1][N]
+ *   naive   : f_t,                    Q basis  [L + 1][N]
+ * A NULL pointer is an all-zero diagonal and is skipped exactly.  The
+ * progression must not repeat an offset: n1 n2 n3 (or n_diag) indices at
+ * most N/2 / gcd(s, N/2).
  */
 typedef struct {
   int n1, n2, n3;                /* split; n3 = 1 for BSGS; ignored by naive */
   int n_diag;                    /* entries in pt                            */
   const uint64_t* const* pt;     /* host [n_diag] of device pointers          */
   double pt_scale;               /* scale the plaintexts were encoded with   */
+  int stride;                    /* s; 0 reads as 1                          */
+  int centre;                    /* c                                        */
 } ckks_lt_diags;
 
 /*
@@ -180,6 +196,114 @@ int ckks_lt_batch_workspace_size(const ckks_params* params, int count, const ckk
  */
 int ckks_lt_eval_batch(const ckks_params* params, int count, ckks_lt_item* items, int algo, void* ws,
                        size_t ws_bytes, void* stream);
+
+/* ---- continuous-batching server ------------------------------------------ */
+/*
+ * A server evaluates TH-BSGS LT requests (Algorithm 2) for callers that
+ * submit them one at a time.  A worker thread owned by the server admits
+ * queued requests, oldest first, into batches evaluated with
+ * ckks_lt_eval_batch, each batch on one of max_inflight streams of its own:
+ * a request that arrives while other batches run is admitted as soon as a
+ * stream is free and its workspace fits in the server's arena.  The arena
+ * is one device allocation of hbm_budget_bytes made at creation; it holds the
+ * workspaces of the batches in flight (ciphertexts, plaintexts, keys and
+ * outputs stay in the caller's device memory).  Requests are admitted in
+ * arrival order: a request whose workspace does not fit yet waits (those
+ * behind it wait too), a request whose workspace alone exceeds the budget is
+ * refused at submission.  Results are bit-identical to evaluating the request
+ * alone with ckks_lt_eval.
+ *
+ * backend CKKS_SERVER_DEVICE runs on the device current at creation.
+ * CKKS_SERVER_SIMULATED does no device work and allocates nothing: a batch of
+ * b requests "runs" for simulated_service_s * (1 + (b-1)/4) seconds and
+ * request workspaces are the sim_ws_bytes the caller states; it exists to
+ * exercise admission and batching on hosts without a device.
+ */
+#define CKKS_SERVER_DEVICE 0
+#define CKKS_SERVER_SIMULATED 1
+
+typedef struct {
+  int backend;              /* CKKS_SERVER_DEVICE or CKKS_SERVER_SIMULATED      */
+  size_t hbm_budget_bytes;  /* workspace arena bytes                           */
+  int max_batch;            /* requests per batch, >= 1                        */
+  int max_inflight;         /* batches on the device at once, 1 .. 16          */
+  double queue_timeout_s;   /* a request still queued after this long fails
+                               with CKKS_E_TIMEOUT; <= 0: no limit            */
+  double simulated_service_s;
+} ckks_server_cfg;
+
+typedef struct ckks_server ckks_server;  /* opaque */
+
+/* One LT request: the fields of a ckks_lt_item plus the ring it runs on. */
+typedef struct {
+  int ring;               /* id from ckks_server_add_ring                      */
+  ckks_ct in;             /* device; complete before submission                */
+  ckks_lt_diags diags;    /* TH-BSGS split; pt array is copied at submission   */
+  ckks_ct out;            /* device; written when the request completes        */
+  size_t sim_ws_bytes;    /* simulated backend only: the request's workspace   */
+} ckks_request;
+
+/*
+ * Creates a server (and its worker thread).  Errors: CKKS_E_INVALID_ARG,
+ * CKKS_E_NOMEM (arena allocation), CKKS_E_DEVICE.
+ */
+int ckks_server_create(const ckks_server_cfg* cfg, ckks_server** out);
+
+/*
+ * Registers a ring: a parameter set and its resident rotation keys (the
+ * rot array and the key pointer array are copied; the key buffers are the
+ * caller's and stay alive and unmodified until ckks_server_destroy).  params
+ * may be NULL for the simulated backend.  Writes the ring id.
+ */
+int ckks_server_add_ring(ckks_server* server, const ckks_params* params, const ckks_rotkeys* keys, int* ring_id);
+
+/*
+ * Queues a request and returns at once (never waits for the device).  The
+ * caller keeps the request's buffers alive until it has finished.  Errors:
+ * CKKS_E_INVALID_ARG (unknown ring, bad level or split), CKKS_E_WORKSPACE
+ * (the request's workspace exceeds the budget).
+ */
+int ckks_server_submit(ckks_server* server, const ckks_request* request, uint64_t* id);
+
+/*
+ * Request state: CKKS_PENDING, CKKS_RUNNING, or its result (CKKS_OK or a
+ * negative code; then out holds the LT and *latency_s, if not NULL, the
+ * seconds from submission to completion, else -1).
+ */
+int ckks_server_poll(ckks_server* server, uint64_t id, int* status, double* latency_s);
+
+/*
+ * The output ciphertext of a finished request, with its level and scale set
+ * (level l-1, scale = in.scale * pt_scale / q_l).  Returns the request's
+ * error code if it failed, CKKS_E_INVALID_ARG if it has not finished.
+ */
+int ckks_server_result(ckks_server* server, uint64_t id, ckks_ct* out);
+
+/* Cancels a request that is still queued (CKKS_E_INVALID_ARG otherwise). */
+int ckks_server_cancel(ckks_server* server, uint64_t id);
+
+/* Blocks until nothing is queued or in flight. */
+int ckks_server_wait_all(ckks_server* server);
+
+typedef struct {
+  long completed;          /* requests finished with CKKS_OK                  */
+  long failed;             /* finished with an error, timed out or cancelled  */
+  long rejected;           /* refused at submission                           */
+  long queued, inflight;   /* requests waiting / running now                  */
+  long batches;            /* batches launched                                */
+  long max_batch;          /* largest batch launched                          */
+  long max_inflight;       /* most batches in flight at once                  */
+  size_t arena_in_use;     /* arena bytes held by batches in flight           */
+  size_t arena_peak;       /* most arena bytes held at once                   */
+  double p50_s, p99_s;     /* latency percentiles of completed requests       */
+  double mean_s;
+  double span_s;           /* first submission to last completion             */
+} ckks_server_stat;
+
+int ckks_server_stats(ckks_server* server, ckks_server_stat* stat);
+
+/* Drains queued and running requests, stops the worker, frees the arena. */
+void ckks_server_destroy(ckks_server* server);
 
 /* ---- the steps of the path, one call each (for tests and composition) ---- */
 /*

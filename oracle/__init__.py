@@ -262,30 +262,42 @@ class Oracle:
         for d, z in diags.items():
             m = idx_of[d]
             f = self.encode_plain(z, scale, basis)
-            G = giant_of.get(m, 0)
+            G = giant_of.get(m, 0) % (self.n // 2)
             out[m] = self.automorph_ntt(f, -G) if G else f
         return out
 
-    def th_plaintexts(self, diags, n1: int, n2: int, n3: int, scale: float):
-        """Algorithm 2 input: f^_{n1 n2 k + n1 j + i} = phi_{-n1 n2 k}(f), at PQ (K_max limbs)."""
-        n = n1 * n2 * n3
+    def _prog_index(self, diags, n: int, stride: int, centre: int) -> Dict[int, int]:
+        """Index t of each cyclic offset d = stride (t - centre) mod S."""
         S = self.n // 2
-        idx_of = {d: d for d in diags}
-        assert all(d < n for d in diags), "diagonal offset beyond the split"
-        giant_of = {m: n1 * n2 * (m // (n1 * n2)) for m in range(n)}
+        idx = {}
+        for t in range(n):
+            d = (stride * (t - centre)) % S
+            assert d not in idx, "the progression repeats an offset"
+            idx[d] = t
+        missing = [d for d in diags if d % S not in idx]
+        assert not missing, "diagonal offsets outside the progression: %r" % missing[:4]
+        return {d: idx[d % S] for d in diags}
+
+    def th_plaintexts(self, diags, n1: int, n2: int, n3: int, scale: float, stride: int = 1, centre: int = 0):
+        """Algorithm 2 input: f^_{n1 n2 k + n1 j + i} = phi_{-G_k}(f), at PQ (K_max
+        limbs), G_k = stride (n1 n2 k - centre); index t holds offset stride (t - centre)."""
+        n = n1 * n2 * n3
+        idx_of = self._prog_index(diags, n, stride, centre)
+        giant_of = {m: stride * (n1 * n2 * (m // (n1 * n2)) - centre) for m in range(n)}
         return self.plaintexts(diags, idx_of, giant_of, n, scale, self.pq_basis(self.L))
 
-    def bsgs_plaintexts(self, diags, n1: int, n2: int, scale: float):
-        """Eq. (5) input: f^_{n1 j + i} = phi_{-n1 j}(f), at Q (L+1 limbs)."""
+    def bsgs_plaintexts(self, diags, n1: int, n2: int, scale: float, stride: int = 1, centre: int = 0):
+        """Eq. (5) input: f^_{n1 j + i} = phi_{-G_j}(f), at Q (L+1 limbs), G_j = stride (n1 j - centre)."""
         n = n1 * n2
-        idx_of = {d: d for d in diags}
-        assert all(d < n for d in diags)
-        giant_of = {m: n1 * (m // n1) for m in range(n)}
+        idx_of = self._prog_index(diags, n, stride, centre)
+        giant_of = {m: stride * (n1 * (m // n1) - centre) for m in range(n)}
         return self.plaintexts(diags, idx_of, giant_of, n, scale, self.q_basis(self.L))
 
-    def naive_plaintexts(self, diags, scale: float):
-        n = max(diags) + 1
-        return self.plaintexts(diags, {d: d for d in diags}, {}, n, scale, self.q_basis(self.L))
+    def naive_plaintexts(self, diags, scale: float, stride: int = 1, centre: int = 0, n: int = None):
+        if n is None:
+            n = max(diags) + 1
+        idx_of = self._prog_index(diags, n, stride, centre)
+        return self.plaintexts(diags, idx_of, {}, n, scale, self.q_basis(self.L))
 
     # ---- linear transformations -----------------------------------------------
     @staticmethod
@@ -298,32 +310,37 @@ class Oracle:
     def _trunc(self, pts):
         return [None if f is None else np.ascontiguousarray(f) for f in pts]
 
-    def lt_th(self, level: int, ct: np.ndarray, split: Tuple[int, int, int], pts, keys) -> np.ndarray:
+    def lt_th(self, level: int, ct: np.ndarray, split: Tuple[int, int, int], pts, keys, stride: int = 1,
+              centre: int = 0) -> np.ndarray:
         n1, n2, n3 = split
         ct = np.ascontiguousarray(ct, dtype=np.uint64)
         out = np.empty((2, level, self.n), dtype=np.uint64)
         pts = self._trunc(pts)
         nk, r, kp = self._keys(keys)
-        _check(lib().orc_lt_th(self.ctx, level, _p(ct[0]), _p(ct[1]), n1, n2, n3, len(pts), _ptr_array(pts),
+        _check(lib().orc_lt_th(self.ctx, level, _p(ct[0]), _p(ct[1]), n1, n2, n3, ctypes.c_long(stride),
+                               ctypes.c_long(centre), len(pts), _ptr_array(pts),
                                nk, r, kp, _p(out[0]), _p(out[1])))
         return out
 
-    def lt_bsgs(self, level: int, ct: np.ndarray, split: Tuple[int, int], pts, keys) -> np.ndarray:
+    def lt_bsgs(self, level: int, ct: np.ndarray, split: Tuple[int, int], pts, keys, stride: int = 1,
+                centre: int = 0) -> np.ndarray:
         n1, n2 = split
         ct = np.ascontiguousarray(ct, dtype=np.uint64)
         out = np.empty((2, level, self.n), dtype=np.uint64)
         pts = self._trunc(pts)
         nk, r, kp = self._keys(keys)
-        _check(lib().orc_lt_bsgs(self.ctx, level, _p(ct[0]), _p(ct[1]), n1, n2, len(pts), _ptr_array(pts),
+        _check(lib().orc_lt_bsgs(self.ctx, level, _p(ct[0]), _p(ct[1]), n1, n2, ctypes.c_long(stride),
+                                 ctypes.c_long(centre), len(pts), _ptr_array(pts),
                                  nk, r, kp, _p(out[0]), _p(out[1])))
         return out
 
-    def lt_naive(self, level: int, ct: np.ndarray, pts, keys) -> np.ndarray:
+    def lt_naive(self, level: int, ct: np.ndarray, pts, keys, stride: int = 1, centre: int = 0) -> np.ndarray:
         ct = np.ascontiguousarray(ct, dtype=np.uint64)
         out = np.empty((2, level, self.n), dtype=np.uint64)
         pts = self._trunc(pts)
         nk, r, kp = self._keys(keys)
-        _check(lib().orc_lt_naive(self.ctx, level, _p(ct[0]), _p(ct[1]), len(pts), _ptr_array(pts),
+        _check(lib().orc_lt_naive(self.ctx, level, _p(ct[0]), _p(ct[1]), ctypes.c_long(stride),
+                                  ctypes.c_long(centre), len(pts), _ptr_array(pts),
                                   nk, r, kp, _p(out[0]), _p(out[1])))
         return out
 

@@ -453,15 +453,33 @@ struct Diags {
   std::vector<const uint64_t*> f;  // f[m] = plaintext for index m (NULL = zero diagonal)
 };
 
+// Diagonal index t stands for the cyclic offset stride*(t - centre) (mod S).
+// Plain Algorithm 2 has stride 1 and centre 0; a strided, centred
+// progression serves sparse matrices such as the factors of a DFT.  The
+// baby and middle rotations become stride*i and stride*n1*j, and the giant
+// rotation of block k becomes G_k = stride*(B k - centre) with B the block
+// length (n1 n2 for TH-BSGS, n1 for BSGS); a block whose G_k vanishes mod S
+// is added without rotation (the role of the k = 0 block in the plain case).
+struct Prog {
+  long stride = 1, centre = 0;
+};
+
+long mod_slots(const Ctx& c, long r) {
+  const long S = c.n / 2;
+  return ((r % S) + S) % S;
+}
+
 // ---------------------------------------------------------------------------
 // Triple-hoisted BSGS (Algorithm 2).  Plaintexts f^_m at PQ (K_max limbs,
-// prefix-truncated to the level), m = n1 n2 k + n1 j + i.
+// prefix-truncated to the level), m = n1 n2 k + n1 j + i, pre-rotated by
+// phi_{-G_k}.
 // ---------------------------------------------------------------------------
-void lt_th(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, int n3,
+void lt_th(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, int n3, Prog pg,
            const Diags& D, const KeyMap& km, uint64_t* o0, uint64_t* o1) {
   const int n = c.n, K = c.K(level), beta = c.beta(level), inner = n1 * n2;
   const size_t PL = (size_t)K * n;
   const std::vector<int> PQ = pq_basis(c, level);
+  const long s = pg.stride;
   auto has = [&](int m) { return m < D.n && D.f[m] != nullptr; };
   // Which baby/middle products feed at least one present diagonal.
   std::vector<char> used_m(inner, 0);
@@ -480,47 +498,45 @@ void lt_th(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, in
   p_scale(c, level, c0, A[0].data());
   p_scale(c, level, c1, B[0].data());
   std::vector<Vec> Dg(n1);
-  // Lines 3-7: inner rotations share d_0; b_i goes through ModDown then Decompose.
+  // Lines 3-7: inner rotations by s*i share d_0; b_i goes through ModDown then Decompose.
   for (int i = 1; i < n1; ++i) {
     if (!used_i[i]) continue;
-    const uint64_t* key = need_key(c, km, i);
+    const long r = s * i;
+    const uint64_t* key = need_key(c, km, r);
     Vec x(PL), y(PL);
     ks_inner(c, level, d0.data(), key, x.data(), y.data());
     add_inplace(c, PQ, x.data(), A[0].data());
     A[i].resize(PL); B[i].resize(PL);
-    automorph_ntt(c, i, x.data(), A[i].data(), K);
-    automorph_ntt(c, i, y.data(), B[i].data(), K);
+    automorph_ntt(c, r, x.data(), A[i].data(), K);
+    automorph_ntt(c, r, y.data(), B[i].data(), K);
     if (!mid_i[i]) continue;
     Vec bq((size_t)(level + 1) * n);
     moddown(c, level, B[i].data(), bq.data());
     Dg[i].resize((size_t)beta * PL);
     decompose(c, level, bq.data(), Dg[i].data());
   }
-  // Lines 8-11: middle rotations by n1 j share d_i.
+  // Lines 8-11: middle rotations by s*n1*j share d_i.
   for (int i = 0; i < n1; ++i) {
     if (!mid_i[i]) continue;
     const uint64_t* di = (i == 0) ? d0.data() : Dg[i].data();
     for (int j = 1; j < n2; ++j) {
       int m = n1 * j + i;
       if (!used_m[m]) continue;
-      const uint64_t* key = need_key(c, km, (long)n1 * j);
+      const long r = s * n1 * j;
+      const uint64_t* key = need_key(c, km, r);
       Vec x(PL), y(PL);
       ks_inner(c, level, di, key, x.data(), y.data());
       add_inplace(c, PQ, x.data(), A[i].data());
       A[m].resize(PL); B[m].resize(PL);
-      automorph_ntt(c, (long)n1 * j, x.data(), A[m].data(), K);
-      automorph_ntt(c, (long)n1 * j, y.data(), B[m].data(), K);
+      automorph_ntt(c, r, x.data(), A[m].data(), K);
+      automorph_ntt(c, r, y.data(), B[m].data(), K);
     }
   }
-  // Line 12: (c0, c1) = sum_{m < n1 n2} (a_m, b_m) f^_m.
+  // Lines 12-18: (u0_k, u1_k) = sum_{m < n1 n2} (a_m, b_m) f^_{n1 n2 k + m};
+  // the block with G_k = 0 is added as is (line 12), every other one after
+  // ModDown, Decompose and the hoisted rotation by G_k.
   Vec C0(PL, 0), C1(PL, 0);
-  for (int m = 0; m < inner; ++m) {
-    if (!has(m)) continue;
-    mac_inplace(c, PQ, C0.data(), A[m].data(), D.f[m]);
-    mac_inplace(c, PQ, C1.data(), B[m].data(), D.f[m]);
-  }
-  // Lines 13-18: outer rotations by n1 n2 k.
-  for (int k = 1; k < n3; ++k) {
+  for (int k = 0; k < n3; ++k) {
     bool any = false;
     for (int m = 0; m < inner; ++m) any |= has(k * inner + m);
     if (!any) continue;
@@ -530,10 +546,15 @@ void lt_th(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, in
       mac_inplace(c, PQ, U0.data(), A[m].data(), D.f[k * inner + m]);
       mac_inplace(c, PQ, U1.data(), B[m].data(), D.f[k * inner + m]);
     }
+    const long G = mod_slots(c, s * ((long)inner * k - pg.centre));
+    if (G == 0) {
+      add_inplace(c, PQ, C0.data(), U0.data());
+      add_inplace(c, PQ, C1.data(), U1.data());
+      continue;
+    }
     Vec u1q((size_t)(level + 1) * n), d((size_t)beta * PL);
     moddown(c, level, U1.data(), u1q.data());
     decompose(c, level, u1q.data(), d.data());
-    long G = (long)inner * k;
     const uint64_t* key = need_key(c, km, G);
     Vec x(PL), y(PL), t(PL);
     ks_inner(c, level, d.data(), key, x.data(), y.data());
@@ -549,9 +570,10 @@ void lt_th(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, in
 }
 
 // ---------------------------------------------------------------------------
-// Plain BSGS, eq. (5): f^_{n1 j + i} = phi_{-n1 j}(f) at Q (L+1 limbs, prefix).
+// Plain BSGS, eq. (5): f^_{n1 j + i} = phi_{-G_j}(f) at Q (L+1 limbs, prefix),
+// baby rotations s*i, giant rotations G_j = s*(n1 j - centre).
 // ---------------------------------------------------------------------------
-void lt_bsgs(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2,
+void lt_bsgs(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, Prog pg,
              const Diags& D, const KeyMap& km, uint64_t* o0, uint64_t* o1) {
   const int n = c.n, Lq = level + 1;
   const size_t QL = (size_t)Lq * n;
@@ -564,7 +586,7 @@ void lt_bsgs(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
   for (int i = 1; i < n1; ++i) {
     if (!used_i[i]) continue;
     R0[i].resize(QL); R1[i].resize(QL);
-    rotate(c, level, c0, c1, i, km, R0[i].data(), R1[i].data());
+    rotate(c, level, c0, c1, pg.stride * i, km, R0[i].data(), R1[i].data());
   }
   Vec A0(QL, 0), A1(QL, 0);
   for (int j = 0; j < n2; ++j) {
@@ -577,12 +599,13 @@ void lt_bsgs(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
       mac_inplace(c, Q, S0.data(), R0[i].data(), D.f[n1 * j + i]);
       mac_inplace(c, Q, S1.data(), R1[i].data(), D.f[n1 * j + i]);
     }
-    if (j == 0) {
+    const long G = mod_slots(c, pg.stride * ((long)n1 * j - pg.centre));
+    if (G == 0) {
       add_inplace(c, Q, A0.data(), S0.data());
       add_inplace(c, Q, A1.data(), S1.data());
     } else {
       Vec T0(QL), T1(QL);
-      rotate(c, level, S0.data(), S1.data(), (long)n1 * j, km, T0.data(), T1.data());
+      rotate(c, level, S0.data(), S1.data(), G, km, T0.data(), T1.data());
       add_inplace(c, Q, A0.data(), T0.data());
       add_inplace(c, Q, A1.data(), T1.data());
     }
@@ -591,19 +614,20 @@ void lt_bsgs(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
   rescale(c, level, A1.data(), o1);
 }
 
-// Diagonal method: out = rescale(sum_d Rot(ct, d) f_d), f_d at Q.
-void lt_naive(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, const Diags& D,
+// Diagonal method: out = rescale(sum_t Rot(ct, s (t - centre)) f_t), f_t at Q.
+void lt_naive(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, Prog pg, const Diags& D,
               const KeyMap& km, uint64_t* o0, uint64_t* o1) {
   const int n = c.n, Lq = level + 1;
   const size_t QL = (size_t)Lq * n;
   const std::vector<int> Q = q_basis(c, level);
   Vec A0(QL, 0), A1(QL, 0), R0(QL), R1(QL);
-  for (int d = 0; d < D.n; ++d) {
-    if (!D.f[d]) continue;
+  for (int t = 0; t < D.n; ++t) {
+    if (!D.f[t]) continue;
+    const long d = mod_slots(c, pg.stride * (t - pg.centre));
     if (d == 0) { R0.assign(c0, c0 + QL); R1.assign(c1, c1 + QL); }
     else rotate(c, level, c0, c1, d, km, R0.data(), R1.data());
-    mac_inplace(c, Q, A0.data(), R0.data(), D.f[d]);
-    mac_inplace(c, Q, A1.data(), R1.data(), D.f[d]);
+    mac_inplace(c, Q, A0.data(), R0.data(), D.f[t]);
+    mac_inplace(c, Q, A1.data(), R1.data(), D.f[t]);
   }
   rescale(c, level, A0.data(), o0);
   rescale(c, level, A1.data(), o1);
@@ -811,21 +835,25 @@ int orc_rotate(void* cv, int level, const uint64_t* c0, const uint64_t* c1, long
   ORC_TRY(rotate(*as_ctx(cv), level, c0, c1, r, make_keys(nkeys, rots, keys), o0, o1))
 }
 
-int orc_lt_th(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, int n3, int nd,
-              const uint64_t* const* diags, int nkeys, const long* rots, const uint64_t* const* keys,
-              uint64_t* o0, uint64_t* o1) {
-  ORC_TRY(lt_th(*as_ctx(cv), level, c0, c1, n1, n2, n3, make_diags(nd, diags), make_keys(nkeys, rots, keys), o0, o1))
+int orc_lt_th(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, int n3, long stride,
+              long centre, int nd, const uint64_t* const* diags, int nkeys, const long* rots,
+              const uint64_t* const* keys, uint64_t* o0, uint64_t* o1) {
+  ORC_TRY(lt_th(*as_ctx(cv), level, c0, c1, n1, n2, n3, Prog{stride, centre}, make_diags(nd, diags),
+                make_keys(nkeys, rots, keys), o0, o1))
 }
 
-int orc_lt_bsgs(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, int nd,
-                const uint64_t* const* diags, int nkeys, const long* rots, const uint64_t* const* keys,
-                uint64_t* o0, uint64_t* o1) {
-  ORC_TRY(lt_bsgs(*as_ctx(cv), level, c0, c1, n1, n2, make_diags(nd, diags), make_keys(nkeys, rots, keys), o0, o1))
+int orc_lt_bsgs(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, long stride,
+                long centre, int nd, const uint64_t* const* diags, int nkeys, const long* rots,
+                const uint64_t* const* keys, uint64_t* o0, uint64_t* o1) {
+  ORC_TRY(lt_bsgs(*as_ctx(cv), level, c0, c1, n1, n2, Prog{stride, centre}, make_diags(nd, diags),
+                  make_keys(nkeys, rots, keys), o0, o1))
 }
 
-int orc_lt_naive(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int nd, const uint64_t* const* diags,
-                 int nkeys, const long* rots, const uint64_t* const* keys, uint64_t* o0, uint64_t* o1) {
-  ORC_TRY(lt_naive(*as_ctx(cv), level, c0, c1, make_diags(nd, diags), make_keys(nkeys, rots, keys), o0, o1))
+int orc_lt_naive(void* cv, int level, const uint64_t* c0, const uint64_t* c1, long stride, long centre, int nd,
+                 const uint64_t* const* diags, int nkeys, const long* rots, const uint64_t* const* keys,
+                 uint64_t* o0, uint64_t* o1) {
+  ORC_TRY(lt_naive(*as_ctx(cv), level, c0, c1, Prog{stride, centre}, make_diags(nd, diags),
+                   make_keys(nkeys, rots, keys), o0, o1))
 }
 
 // Operation counters since the last reset: [decompose, moddown, ks, ntt, intt, distinct keys].

@@ -23,6 +23,13 @@ CKKS_E_UNSUPPORTED = -2
 CKKS_E_WORKSPACE = -3
 CKKS_E_DEVICE = -4
 CKKS_E_NOMEM = -5
+CKKS_E_TIMEOUT = -6
+CKKS_E_CANCELLED = -7
+CKKS_PENDING = 1
+CKKS_RUNNING = 2
+
+CKKS_SERVER_DEVICE = 0
+CKKS_SERVER_SIMULATED = 1
 
 CKKS_LT_NAIVE = 0
 CKKS_LT_BSGS = 1
@@ -34,7 +41,9 @@ EXPORTED = [
     "ckks_lt_workspace_size", "ckks_lt_eval", "ckks_op_ntt", "ckks_op_decompose", "ckks_op_moddown",
     "ckks_op_rescale", "ckks_op_workspace_size", "ckks_op_keyswitch", "ckks_op_automorph",
     "ckks_profile_enable", "ckks_profile_read", "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch",
-    "ckks_lt_cost_model", "ckks_lt_autotune",
+    "ckks_lt_cost_model", "ckks_lt_autotune", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit",
+    "ckks_server_poll", "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats",
+    "ckks_server_destroy",
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
@@ -62,7 +71,8 @@ class Ct(ctypes.Structure):
 
 class Diags(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("n_diag", ctypes.c_int),
-                ("pt", ctypes.POINTER(ctypes.c_void_p)), ("pt_scale", ctypes.c_double)]
+                ("pt", ctypes.POINTER(ctypes.c_void_p)), ("pt_scale", ctypes.c_double), ("stride", ctypes.c_int),
+                ("centre", ctypes.c_int)]
 
 
 class RotKeys(ctypes.Structure):
@@ -84,6 +94,24 @@ class LtRates(ctypes.Structure):
 class LtItem(ctypes.Structure):
     _fields_ = [("in_", Ct), ("diags", Diags), ("keys", ctypes.POINTER(RotKeys)), ("out", Ct),
                 ("status", ctypes.c_int)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("backend", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
+                ("max_inflight", ctypes.c_int), ("queue_timeout_s", ctypes.c_double),
+                ("simulated_service_s", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("ring", ctypes.c_int), ("in_", Ct), ("diags", Diags), ("out", Ct), ("sim_ws_bytes", ctypes.c_size_t)]
+
+
+class ServerStat(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_long), ("failed", ctypes.c_long), ("rejected", ctypes.c_long),
+                ("queued", ctypes.c_long), ("inflight", ctypes.c_long), ("batches", ctypes.c_long),
+                ("max_batch", ctypes.c_long), ("max_inflight", ctypes.c_long), ("arena_in_use", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("mean_s", ctypes.c_double), ("span_s", ctypes.c_double)]
 
 
 _lib = None
@@ -132,6 +160,18 @@ def lib() -> ctypes.CDLL:
         L.ckks_lt_cost_model.argtypes = [ctypes.c_int] * 8 + [ctypes.POINTER(LtCost)]
         L.ckks_lt_autotune.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(LtRates)] + \
             [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)]
+        L.ckks_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
+        L.ckks_server_add_ring.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(RotKeys),
+                                           ctypes.POINTER(ctypes.c_int)]
+        L.ckks_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.ckks_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.ckks_server_result.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Ct)]
+        L.ckks_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        L.ckks_server_wait_all.argtypes = [ctypes.c_void_p]
+        L.ckks_server_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServerStat)]
+        L.ckks_server_destroy.argtypes = [ctypes.c_void_p]
+        L.ckks_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -209,10 +249,11 @@ def ckks_params_info(params: Params) -> Tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
-def _diags(split: Sequence[int], pts: Sequence, pt_scale: float):
+def _diags(split: Sequence[int], pts: Sequence, pt_scale: float, stride: int = 1, centre: int = 0):
     n1, n2, n3 = (list(split) + [1, 1])[:3]
     arr = (ctypes.c_void_p * max(1, len(pts)))(*[_ptr(x) for x in pts])
-    return Diags(n1, n2, n3, len(pts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), pt_scale), arr
+    return Diags(n1, n2, n3, len(pts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), pt_scale, stride,
+                 centre), arr
 
 
 def _keys(keys: Optional[Dict[int, object]]):
@@ -224,8 +265,9 @@ def _keys(keys: Optional[Dict[int, object]]):
                    ctypes.cast(k, ctypes.POINTER(ctypes.c_void_p))), (r, k)
 
 
-def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts: Sequence, algo: int) -> int:
-    d, keep = _diags(split, pts, 1.0)
+def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts: Sequence, algo: int,
+                           stride: int = 1, centre: int = 0) -> int:
+    d, keep = _diags(split, pts, 1.0, stride, centre)
     out = ctypes.c_size_t()
     _check(lib().ckks_lt_workspace_size(params, level, ctypes.byref(d), algo, ctypes.byref(out)),
            "ckks_lt_workspace_size")
@@ -234,11 +276,11 @@ def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts
 
 def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequence[int], pts: Sequence,
                  pt_scale: float, keys: Optional[Dict[int, object]], algo: int, out0, out1, ws, ws_bytes: int,
-                 stream=None) -> Tuple[int, float]:
+                 stream=None, stride: int = 1, centre: int = 0) -> Tuple[int, float]:
     """Enqueue out = LT(in); returns (out level, out scale)."""
     cin = Ct(level, scale, _ptr(c0), _ptr(c1))
     cout = Ct(level - 1, 0.0, _ptr(out0), _ptr(out1))
-    d, keep1 = _diags(split, pts, pt_scale)
+    d, keep1 = _diags(split, pts, pt_scale, stride, centre)
     k, keep2 = _keys(keys)
     _check(lib().ckks_lt_eval(params, ctypes.byref(cin), ctypes.byref(d), ctypes.byref(k), algo,
                               ctypes.byref(cout), _ptr(ws), ws_bytes, _stream(stream)), "ckks_lt_eval")
@@ -248,8 +290,9 @@ def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequen
 class BatchItem:
     """One LT of a batch (device buffers as tensors or int addresses)."""
 
-    def __init__(self, level, scale, c0, c1, split, pts, pt_scale, keys, out0, out1):
+    def __init__(self, level, scale, c0, c1, split, pts, pt_scale, keys, out0, out1, stride=1, centre=0):
         self.level, self.scale, self.c0, self.c1 = level, scale, c0, c1
+        self.stride, self.centre = stride, centre
         self.split, self.pts, self.pt_scale, self.keys = split, pts, pt_scale, keys
         self.out0, self.out1 = out0, out1
         self.status = None
@@ -260,7 +303,7 @@ def _items(items: Sequence[BatchItem]):
     arr = (LtItem * max(1, len(items)))()
     keep = []
     for t, it in enumerate(items):
-        d, k1 = _diags(it.split, it.pts, it.pt_scale)
+        d, k1 = _diags(it.split, it.pts, it.pt_scale, it.stride, it.centre)
         ks, k2 = _keys(it.keys)
         keep += [d, k1, ks, k2]
         arr[t].in_ = Ct(it.level, it.scale, _ptr(it.c0), _ptr(it.c1))
@@ -288,6 +331,89 @@ def ckks_lt_eval_batch(params: Params, items: Sequence[BatchItem], algo: int, ws
         it.status = arr[t].status
         it.out_level, it.out_scale = arr[t].out.level, arr[t].out.scale
     return code
+
+
+class Server:
+    """Owns a ckks_server handle; the ctypes arrays of registered rings are
+    kept alive here for the server's lifetime."""
+
+    def __init__(self, budget_bytes: int, max_batch: int = 8, max_inflight: int = 2, simulated: bool = False,
+                 queue_timeout_s: float = 0.0, simulated_service_s: float = 0.0):
+        cfg = ServerCfg(CKKS_SERVER_SIMULATED if simulated else CKKS_SERVER_DEVICE, budget_bytes, max_batch,
+                        max_inflight, queue_timeout_s, simulated_service_s)
+        h = ctypes.c_void_p()
+        _check(lib().ckks_server_create(ctypes.byref(cfg), ctypes.byref(h)), "ckks_server_create")
+        self.handle = h
+        self._keep = []
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+    def close(self):
+        if self.handle:
+            lib().ckks_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ckks_server_add_ring(server: Server, params: Optional[Params], keys: Optional[Dict[int, object]]) -> int:
+    k, keep = _keys(keys)
+    server._keep += [k, keep]
+    rid = ctypes.c_int()
+    _check(lib().ckks_server_add_ring(server, params, ctypes.byref(k), ctypes.byref(rid)), "ckks_server_add_ring")
+    return rid.value
+
+
+def ckks_server_submit(server: Server, ring: int, level: int = 0, scale: float = 0.0, c0=None, c1=None,
+                       split: Sequence[int] = (1, 1, 1), pts: Sequence = (), pt_scale: float = 0.0, out0=None,
+                       out1=None, sim_ws_bytes: int = 0, stride: int = 1, centre: int = 0) -> int:
+    """Queue one TH-BSGS LT; returns the request id (raises if refused)."""
+    d, keep = _diags(split, pts, pt_scale, stride, centre)
+    rq = Request(ring, Ct(level, scale, _ptr(c0), _ptr(c1)), d, Ct(level - 1, 0.0, _ptr(out0), _ptr(out1)),
+                 sim_ws_bytes)
+    rid = ctypes.c_uint64()
+    _check(lib().ckks_server_submit(server, ctypes.byref(rq), ctypes.byref(rid)), "ckks_server_submit")
+    return rid.value
+
+
+def ckks_server_poll(server: Server, rid: int) -> Tuple[int, float]:
+    """(status, latency seconds or -1)."""
+    st, lat = ctypes.c_int(), ctypes.c_double()
+    _check(lib().ckks_server_poll(server, rid, ctypes.byref(st), ctypes.byref(lat)), "ckks_server_poll")
+    return st.value, lat.value
+
+
+def ckks_server_result(server: Server, rid: int) -> Tuple[int, float]:
+    """(level, scale) of a finished request's output."""
+    c = Ct()
+    _check(lib().ckks_server_result(server, rid, ctypes.byref(c)), "ckks_server_result")
+    return c.level, c.scale
+
+
+def ckks_server_cancel(server: Server, rid: int) -> int:
+    return lib().ckks_server_cancel(server, rid)
+
+
+def ckks_server_wait_all(server: Server):
+    _check(lib().ckks_server_wait_all(server), "ckks_server_wait_all")
+
+
+def ckks_server_stats(server: Server) -> dict:
+    st = ServerStat()
+    _check(lib().ckks_server_stats(server, ctypes.byref(st)), "ckks_server_stats")
+    return {f: getattr(st, f) for f, _ in ServerStat._fields_}
 
 
 def ckks_lt_cost_model(log_n: int, level: int, alpha: int, algo: int, split: Sequence[int], word_bits: int = 64) -> dict:

@@ -407,11 +407,16 @@ struct Diag {
 
 // ---- triple-hoisted BSGS, Algorithm 2, for one or many ciphertexts ----------------
 
+// Index t of the diagonals stands for the cyclic offset stride (t - centre):
+// rotations s i (inner), s n1 j (middle) and G_k = s (n1 n2 k - centre)
+// (outer); a block whose G_k vanishes mod N/2 is added without rotation.
 struct ThItem {
   int level;
   const uint64_t* c0;
   const uint64_t* c1;
   int n1, n2, n3;
+  long stride = 1, centre = 0;
+  int kdir = -1;  // the block with G_k = 0, or -1
   Diag D;
   const KeySet* ks;
   uint64_t* o0;
@@ -421,6 +426,12 @@ struct ThItem {
   bool need_d0 = false;
   // buffers
   std::vector<uint64_t*> Dg, A, B, U0, U1, tmpQ, tmpK, Dk;
+  uint64_t* acc0 = nullptr;  // (c0, c1) of lines 12-18 at PQ
+  uint64_t* acc1 = nullptr;
+  long giant(const ckks_params* P, int k) const {
+    const long S = P->n / 2;
+    return (((stride * ((long)n1 * n2 * k - centre)) % S) + S) % S;
+  }
 };
 
 void lt_th(Run& R, std::vector<ThItem>& items) {
@@ -442,6 +453,9 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
       }
     it.need_d0 = it.mid_i[0];
     for (int i = 1; i < it.n1; ++i) it.need_d0 = it.need_d0 || it.used_i[i];
+    it.kdir = -1;
+    for (int k = 0; k < it.n3 && it.kdir < 0; ++k)
+      if (it.giant(P, k) == 0) it.kdir = k;
     it.Dg.assign(it.n1, nullptr);
     it.A.assign(inner, nullptr);
     it.B.assign(inner, nullptr);
@@ -460,13 +474,20 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     it.tmpK.assign(it.n3, nullptr);
     it.Dk.assign(it.n3, nullptr);
     for (int k = 0; k < it.n3; ++k) {
-      if (k > 0 && !it.used_k[k]) continue;
+      if (k != it.kdir && !it.used_k[k]) continue;
       it.U0[k] = R.limbs(K);
       it.U1[k] = R.limbs(K);
-      if (k > 0) {
+      if (k != it.kdir) {
         it.tmpK[k] = R.limbs(Lq);
         it.Dk[k] = R.limbs((size_t)beta * K);
       }
+    }
+    if (it.kdir >= 0) {
+      it.acc0 = it.U0[it.kdir];
+      it.acc1 = it.U1[it.kdir];
+    } else {
+      it.acc0 = R.limbs(K);
+      it.acc1 = R.limbs(K);
     }
   }
   // Line 1: d_0 = Decompose(c1').
@@ -482,7 +503,8 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     for (ThItem& it : items)
       for (int i = 1; i < it.n1; ++i)
         if (it.used_i[i])
-          tasks.push_back(KsTask{it.Dg[0], it.level, it.c0, true, it.ks->get(R, i), galois(P, -i), it.A[i], it.B[i]});
+          tasks.push_back(KsTask{it.Dg[0], it.level, it.c0, true, it.ks->get(R, it.stride * i),
+                                 galois(P, -it.stride * i), it.A[i], it.B[i]});
     keyswitch(R, tasks);
   }
   // Lines 6-7: d_i = Decompose(ModDown(b_i)), every i at once.
@@ -497,7 +519,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     divide(R, DIV_MODDOWN, md);
     decompose(R, dc);
   }
-  // Lines 8-11: middle rotations by n1 j share d_i; each middle key is read
+  // Lines 8-11: middle rotations by s n1 j share d_i; each middle key is read
   // once per launch for all digit sets.
   {
     std::vector<KsTask> tasks;
@@ -506,42 +528,45 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
         for (int i = 0; i < it.n1; ++i) {
           const int m = it.n1 * j + i;
           if (!it.mid_i[i] || !it.used_m[m]) continue;
-          const long r = (long)it.n1 * j;
+          const long r = it.stride * it.n1 * j;
           tasks.push_back(KsTask{it.Dg[i], it.level, i == 0 ? it.c0 : it.A[i], i == 0, it.ks->get(R, r),
                                  galois(P, -r), it.A[m], it.B[m]});
         }
     keyswitch(R, tasks);
   }
-  // Lines 12 and 14: all plaintext products of an item at once.
+  // Lines 12 and 14: all plaintext products of an item at once (with no
+  // unrotated block, the accumulator is one more output with no plaintext,
+  // i.e. zero).
   for (ThItem& it : items) {
     const int K = P->K(it.level), inner = it.n1 * it.n2;
     std::vector<int> kk;
     for (int k = 0; k < it.n3; ++k)
-      if (k == 0 || it.used_k[k]) kk.push_back(k);
+      if (k == it.kdir || it.used_k[k]) kk.push_back(k);
+    if (it.kdir < 0) kk.push_back(-1);
     std::vector<MacTerm> terms;
     for (int m = 0; m < inner; ++m) {
       if (!it.used_m[m]) continue;
       MacTerm t{m == 0 ? it.c0 : it.A[m], m == 0 ? it.c1 : it.B[m], m == 0, {}};
-      for (int k : kk) t.f.push_back(it.D.has(k * inner + m) ? it.D.pt[k * inner + m] : nullptr);
+      for (int k : kk) t.f.push_back(k >= 0 && it.D.has(k * inner + m) ? it.D.pt[k * inner + m] : nullptr);
       terms.push_back(t);
     }
     // No diagonal at all: the result is an encryption of zero.
     if (terms.empty()) terms.push_back(MacTerm{it.c0, it.c1, true, std::vector<const uint64_t*>(kk.size(), nullptr)});
     std::vector<uint64_t*> o0, o1;
     for (int k : kk) {
-      o0.push_back(it.U0[k]);
-      o1.push_back(it.U1[k]);
+      o0.push_back(k >= 0 ? it.U0[k] : it.acc0);
+      o1.push_back(k >= 0 ? it.U1[k] : it.acc1);
     }
     ptmac(R, K, 0, terms, o0, o1);
   }
-  // Lines 13-18: outer rotations by n1 n2 k: ModDown and Decompose of every
+  // Lines 13-18: outer rotations by G_k: ModDown and Decompose of every
   // (item, k) at once, then per item one gather kernel adds
   // phi_G(u0 + x), phi_G(y) of all its k into (c0, c1).
   {
     Jobs md, dc;
     for (ThItem& it : items)
-      for (int k = 1; k < it.n3; ++k)
-        if (it.used_k[k]) {
+      for (int k = 0; k < it.n3; ++k)
+        if (k != it.kdir && it.used_k[k]) {
           md.push_back({it.level, it.U1[k], it.tmpK[k]});
           dc.push_back({it.level, it.tmpK[k], it.Dk[k]});
         }
@@ -549,18 +574,18 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     decompose(R, dc);
     for (ThItem& it : items) {
       std::vector<int> kk;
-      for (int k = 1; k < it.n3; ++k)
-        if (it.used_k[k]) kk.push_back(k);
+      for (int k = 0; k < it.n3; ++k)
+        if (k != it.kdir && it.used_k[k]) kk.push_back(k);
       for (size_t k0 = 0; k0 < kk.size(); k0 += kMaxKs) {
         KsGatherArgs ga;
         memset(&ga, 0, sizeof(ga));
         ga.beta = P->beta(it.level);
         ga.K = P->K(it.level);
         ga.kmax = P->Kmax();
-        ga.c0 = it.U0[0];
-        ga.c1 = it.U1[0];
+        ga.c0 = it.acc0;
+        ga.c1 = it.acc1;
         for (size_t t = k0; t < std::min(kk.size(), k0 + kMaxKs); ++t) {
-          const long G = (long)it.n1 * it.n2 * kk[t];
+          const long G = it.giant(P, kk[t]);
           ga.digits[ga.nk] = it.Dk[kk[t]];
           ga.key[ga.nk] = it.ks->get(R, G);
           ga.add[ga.nk] = it.U0[kk[t]];
@@ -575,18 +600,25 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
   {
     Jobs md;
     for (ThItem& it : items) {
-      md.push_back({it.level, it.U0[0], it.o0});
-      md.push_back({it.level, it.U1[0], it.o1});
+      md.push_back({it.level, it.acc0, it.o0});
+      md.push_back({it.level, it.acc1, it.o1});
     }
     divide(R, DIV_MODDOWN_RESCALE, md);
   }
 }
 
 // ---- plain BSGS, eq. (5) -------------------------------------------------------
-void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, const Diag& D,
-             const KeySet& ks, uint64_t* o0, uint64_t* o1) {
+// Baby rotations s i, giant rotations G_j = s (n1 j - centre); the block whose
+// G_j vanishes mod N/2 is added without rotation.
+void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, long stride, long centre,
+             const Diag& D, const KeySet& ks, uint64_t* o0, uint64_t* o1) {
   const ckks_params* P = R.P;
   const int Lq = level + 1;
+  const long S = P->n / 2;
+  auto giant = [&](int j) { return (((stride * ((long)n1 * j - centre)) % S) + S) % S; };
+  int jdir = -1;
+  for (int j = 0; j < n2 && jdir < 0; ++j)
+    if (giant(j) == 0) jdir = j;
   std::vector<char> used_i(n1, 0), used_j(n2, 0);
   for (int j = 0; j < n2; ++j)
     for (int i = 0; i < n1; ++i)
@@ -601,70 +633,79 @@ void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
     }
   uint64_t* A0 = R.limbs(Lq);
   uint64_t* A1 = R.limbs(Lq);
-  for (int j = 1; j < n2; ++j)
-    if (used_j[j]) {
+  for (int j = 0; j < n2; ++j)
+    if (used_j[j] && j != jdir) {
       S0[j] = R.limbs(Lq);
       S1[j] = R.limbs(Lq);
     }
-  // Baby steps: ct_i = Rot(ct, i), each with its own Decompose.
+  // Baby steps: ct_i = Rot(ct, s i), each with its own Decompose.
   {
     std::vector<RotJob> jobs;
     for (int i = 1; i < n1; ++i)
-      if (used_i[i]) jobs.push_back(RotJob{c0, c1, (long)i, R0[i], R1[i], false});
+      if (used_i[i]) jobs.push_back(RotJob{c0, c1, stride * i, R0[i], R1[i], false});
     rotate(R, level, jobs, ks);
   }
-  // Inner sums for every giant step at once: A = sum_i ct_i f^_i (j = 0) and
-  // S_j = sum_i ct_i f^_{n1 j + i}.
+  // Inner sums for every giant step at once: A = sum_i ct_i f^_{n1 jdir + i}
+  // (zero if no block is unrotated) and S_j = sum_i ct_i f^_{n1 j + i}.
   {
     std::vector<MacTerm> terms;
-    std::vector<int> js;
-    std::vector<uint64_t*> out0, out1;
+    std::vector<int> js{jdir};
+    std::vector<uint64_t*> out0{A0}, out1{A1};
     for (int j = 0; j < n2; ++j)
-      if (j == 0 || used_j[j]) {
+      if (used_j[j] && j != jdir) {
         js.push_back(j);
-        out0.push_back(j == 0 ? A0 : S0[j]);
-        out1.push_back(j == 0 ? A1 : S1[j]);
+        out0.push_back(S0[j]);
+        out1.push_back(S1[j]);
       }
     for (int i = 0; i < n1; ++i) {
       if (!used_i[i]) continue;
       MacTerm t{R0[i], R1[i], false, {}};
-      for (int j : js) t.f.push_back(D.has(n1 * j + i) ? D.pt[n1 * j + i] : nullptr);
+      for (int j : js) t.f.push_back(j >= 0 && D.has(n1 * j + i) ? D.pt[n1 * j + i] : nullptr);
       terms.push_back(t);
     }
     if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, std::vector<const uint64_t*>(js.size(), nullptr)});
     ptmac(R, Lq, P->alpha, terms, out0, out1);
   }
-  // Giant steps: A += Rot(S_j, n1 j).
+  // Giant steps: A += Rot(S_j, G_j).
   {
     std::vector<RotJob> jobs;
-    for (int j = 1; j < n2; ++j)
-      if (used_j[j]) jobs.push_back(RotJob{S0[j], S1[j], (long)n1 * j, A0, A1, true});
+    for (int j = 0; j < n2; ++j)
+      if (used_j[j] && j != jdir) jobs.push_back(RotJob{S0[j], S1[j], giant(j), A0, A1, true});
     rotate(R, level, jobs, ks);
   }
   divide(R, DIV_RESCALE, Jobs{{level, A0, o0}, {level, A1, o1}});
 }
 
 // ---- diagonal method ---------------------------------------------------------
-void lt_naive(Run& R, int level, const uint64_t* c0, const uint64_t* c1, const Diag& D, const KeySet& ks,
-              uint64_t* o0, uint64_t* o1) {
+// out = rescale(sum_t Rot(ct, s (t - centre)) f_t).
+void lt_naive(Run& R, int level, const uint64_t* c0, const uint64_t* c1, long stride, long centre, const Diag& D,
+              const KeySet& ks, uint64_t* o0, uint64_t* o1) {
   const ckks_params* P = R.P;
   const int Lq = level + 1;
+  const long S = P->n / 2;
   uint64_t* A0 = R.limbs(Lq);
   uint64_t* A1 = R.limbs(Lq);
-  std::vector<int> ds;
-  for (int d = 1; d < D.n; ++d)
-    if (D.has(d)) ds.push_back(d);
-  std::vector<uint64_t*> T0(ds.size()), T1(ds.size());
-  for (size_t t = 0; t < ds.size(); ++t) {
-    T0[t] = R.limbs(Lq);
-    T1[t] = R.limbs(Lq);
+  std::vector<int> ts;
+  int tdir = -1;
+  for (int t = 0; t < D.n; ++t) {
+    if (!D.has(t)) continue;
+    if ((((stride * (t - centre)) % S) + S) % S == 0)
+      tdir = t;
+    else
+      ts.push_back(t);
+  }
+  std::vector<uint64_t*> T0(ts.size()), T1(ts.size());
+  for (size_t u = 0; u < ts.size(); ++u) {
+    T0[u] = R.limbs(Lq);
+    T1[u] = R.limbs(Lq);
   }
   std::vector<RotJob> jobs;
-  for (size_t t = 0; t < ds.size(); ++t) jobs.push_back(RotJob{c0, c1, (long)ds[t], T0[t], T1[t], false});
+  for (size_t u = 0; u < ts.size(); ++u)
+    jobs.push_back(RotJob{c0, c1, stride * (ts[u] - centre), T0[u], T1[u], false});
   rotate(R, level, jobs, ks);
   std::vector<MacTerm> terms;
-  if (D.has(0)) terms.push_back(MacTerm{c0, c1, false, {D.pt[0]}});
-  for (size_t t = 0; t < ds.size(); ++t) terms.push_back(MacTerm{T0[t], T1[t], false, {D.pt[ds[t]]}});
+  if (tdir >= 0) terms.push_back(MacTerm{c0, c1, false, {D.pt[tdir]}});
+  for (size_t u = 0; u < ts.size(); ++u) terms.push_back(MacTerm{T0[u], T1[u], false, {D.pt[ts[u]]}});
   if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, {nullptr}});
   ptmac(R, Lq, P->alpha, terms, {A0}, {A1});
   divide(R, DIV_RESCALE, Jobs{{level, A0, o0}, {level, A1, o1}});
@@ -675,6 +716,9 @@ bool overlap(const void* a, size_t an, const void* b, size_t bn) {
   const uint8_t *x = (const uint8_t*)a, *y = (const uint8_t*)b;
   return x < y + bn && y < x + an;
 }
+
+// A zero stride (a zero-initialised struct) reads as 1.
+long prog_stride(const ckks_lt_diags* d) { return d->stride == 0 ? 1 : d->stride; }
 
 // Validates one LT's arguments (no device access); fills ks from keys.
 int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* diags, const ckks_rotkeys* keys,
@@ -697,6 +741,21 @@ int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* dia
     if (keys->count < 0 || (keys->count > 0 && (!keys->rot || !keys->key))) return CKKS_E_INVALID_ARG;
     for (int i = 0; i < keys->count; ++i) ks->m[((keys->rot[i] % ks->S) + ks->S) % ks->S] = keys->key[i];
   }
+  // The progression stride (t - centre) must not repeat an offset mod N/2:
+  // at most N/2 / gcd(stride, N/2) indices.
+  const long S = P->n / 2;
+  const long st = ((prog_stride(diags) % S) + S) % S;
+  long g = S, x = st;
+  while (x) {
+    const long t = g % x;
+    g = x;
+    x = t;
+  }
+  const long period = S / g;
+  long n_idx = diags->n_diag;
+  if (algo == CKKS_LT_TH_BSGS) n_idx = std::max<long>(n_idx, (long)diags->n1 * diags->n2 * diags->n3);
+  if (algo == CKKS_LT_BSGS || algo == CKKS_LT_DH_BSGS) n_idx = std::max<long>(n_idx, (long)diags->n1 * diags->n2);
+  if (n_idx > period) return CKKS_E_INVALID_ARG;
   if (algo == CKKS_LT_TH_BSGS) {
     const int n1 = diags->n1, n2 = diags->n2, n3 = diags->n3;
     if (n1 < 1 || n2 < 1 || n3 < 1 || (long)n1 * n2 * n3 < diags->n_diag || (long)n1 * n2 * n3 > P->n / 2)
@@ -722,6 +781,8 @@ ThItem th_item(const ckks_ct* in, const ckks_lt_diags* d, const KeySet* ks, ckks
   it.n1 = dh ? 1 : d->n1;
   it.n2 = dh ? d->n1 : d->n2;
   it.n3 = dh ? d->n2 : d->n3;
+  it.stride = prog_stride(d);
+  it.centre = d->centre;
   it.D.n = d->n_diag;
   it.D.pt = d->pt;
   it.ks = ks;
@@ -745,10 +806,12 @@ void run_items(Run& R, int algo, const std::vector<const ckks_ct*>& in, const st
     Diag D;
     D.n = dg[t]->n_diag;
     D.pt = dg[t]->pt;
+    const long stride = prog_stride(dg[t]), centre = dg[t]->centre;
     if (algo == CKKS_LT_BSGS)
-      lt_bsgs(R, in[t]->level, in[t]->c0, in[t]->c1, dg[t]->n1, dg[t]->n2, D, ks[t], out[t]->c0, out[t]->c1);
+      lt_bsgs(R, in[t]->level, in[t]->c0, in[t]->c1, dg[t]->n1, dg[t]->n2, stride, centre, D, ks[t], out[t]->c0,
+              out[t]->c1);
     else
-      lt_naive(R, in[t]->level, in[t]->c0, in[t]->c1, D, ks[t], out[t]->c0, out[t]->c1);
+      lt_naive(R, in[t]->level, in[t]->c0, in[t]->c1, stride, centre, D, ks[t], out[t]->c0, out[t]->c1);
   }
 }
 
@@ -807,6 +870,10 @@ const char* ckks_strerror(int code) {
     case CKKS_E_WORKSPACE: return "workspace too small";
     case CKKS_E_DEVICE: return "HIP runtime error";
     case CKKS_E_NOMEM: return "device allocation failed";
+    case CKKS_E_TIMEOUT: return "request timed out in the queue";
+    case CKKS_E_CANCELLED: return "request cancelled";
+    case CKKS_PENDING: return "pending";
+    case CKKS_RUNNING: return "running";
     default: return "unknown error";
   }
 }

@@ -29,6 +29,28 @@ def random_limbs(seed: int, moduli, n: int) -> np.ndarray:
     return W.uniform_residues(seed, moduli, n)
 
 
+def batch_case(prm: W.Params, specs, seed: int):
+    """Oracle keys, ciphertexts and TH plaintexts for several LTs sharing one
+    key set.  specs: (level, n_diag, split) per item; banded diagonals
+    0 .. n_diag-1.  Returns (oracle, keys, items, delta)."""
+    o = O.Oracle(prm)
+    o.keygen(seed)
+    delta = 2.0 ** prm.log_delta
+    S = prm.slots
+    rots = set()
+    for level, nd, split in specs:
+        rots |= set(W.th_rotations(*split))
+    keys = o.rotkeys(sorted(rots))
+    items = []
+    for t, (level, nd, split) in enumerate(specs):
+        diags = W.banded_diagonals(seed * 100 + t, S, range(nd))
+        v = W.input_vector(seed * 100 + t, S)
+        ct = o.encrypt(level, v, delta, seed=seed * 100 + t)
+        pts = o.th_plaintexts(diags, *split, delta)
+        items.append(dict(level=level, split=split, diags=diags, v=v, ct=ct, pts=pts))
+    return o, keys, items, delta
+
+
 class LTCase:
     """Keys, plaintexts and a ciphertext for one workload, made by the oracle."""
 

@@ -5,32 +5,11 @@ alone), and decrypt to M v within the stated tolerance."""
 import numpy as np
 import pytest
 
-import oracle as O
 import paper_2605_17222_amd as H
 import workload as W
-from gpu_common import gpu_params, limbs_tensor, log
+from gpu_common import batch_case as _batch_case, gpu_params, limbs_tensor, log
 
 pytestmark = pytest.mark.gpu
-
-
-def _batch_case(prm, specs, seed):
-    """specs: list of (level, n_diag, split).  Returns oracle, keys, items data."""
-    o = O.Oracle(prm)
-    o.keygen(seed)
-    delta = 2.0 ** prm.log_delta
-    S = prm.slots
-    rots = set()
-    for level, nd, split in specs:
-        rots |= set(W.th_rotations(*split))
-    keys = o.rotkeys(sorted(rots))
-    items = []
-    for t, (level, nd, split) in enumerate(specs):
-        diags = W.banded_diagonals(seed * 100 + t, S, range(nd))
-        v = W.input_vector(seed * 100 + t, S)
-        ct = o.encrypt(level, v, delta, seed=seed * 100 + t)
-        pts = o.th_plaintexts(diags, *split, delta)
-        items.append(dict(level=level, split=split, diags=diags, v=v, ct=ct, pts=pts))
-    return o, keys, items, delta
 
 
 def _run_gpu(prm, keys, items, delta, only=None):

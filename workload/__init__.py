@@ -17,6 +17,7 @@ parameter sets it evaluates):
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -130,16 +131,22 @@ def params_n16(log_n: int = 16) -> Params:
 # Splits (n1', n2', n3') and rotation sets
 # ----------------------------------------------------------------------------
 
-def th_rotations(n1: int, n2: int, n3: int) -> List[int]:
-    """Rotations whose keys TH-BSGS uses: i (inner), n1*j (middle), n1*n2*k (outer)."""
-    r = [i for i in range(1, n1)]
-    r += [n1 * j for j in range(1, n2)]
-    r += [n1 * n2 * k for k in range(1, n3)]
-    return sorted(set(r))
+def th_rotations(n1: int, n2: int, n3: int, stride: int = 1, centre: int = 0, slots: int = None) -> List[int]:
+    """Rotations whose keys TH-BSGS uses: s*i (inner), s*n1*j (middle) and the
+    non-zero G_k = s*(n1*n2*k - centre) (outer), reduced mod slots if given."""
+    r = [stride * i for i in range(1, n1)]
+    r += [stride * n1 * j for j in range(1, n2)]
+    r += [stride * (n1 * n2 * k - centre) for k in range(n3)]
+    if slots:
+        r = [x % slots for x in r]
+    return sorted(set(x for x in r if x != 0))
 
 
-def bsgs_rotations(n1: int, n2: int) -> List[int]:
-    return sorted(set([i for i in range(1, n1)] + [n1 * j for j in range(1, n2)]))
+def bsgs_rotations(n1: int, n2: int, stride: int = 1, centre: int = 0, slots: int = None) -> List[int]:
+    r = [stride * i for i in range(1, n1)] + [stride * (n1 * j - centre) for j in range(n2)]
+    if slots:
+        r = [x % slots for x in r]
+    return sorted(set(x for x in r if x != 0))
 
 
 # ----------------------------------------------------------------------------
@@ -215,3 +222,58 @@ def workload_n16(seed: int = 1, n_diag: int = 64, level: int = 24,
     return LTWorkload("n%d_l%d_d%d" % (log_n, level, n_diag), prm, level,
                       banded_diagonals(seed, prm.slots, range(n_diag)),
                       input_vector(seed, prm.slots), tuple(th_split), tuple(bsgs_split), seed)
+
+
+@dataclasses.dataclass
+class ChainStage:
+    """One sparse LT of a chain: cyclic diagonals and the TH split over the
+    progression offset(t) = stride (t - centre), t < n1 n2 n3."""
+    diags: Dict[int, np.ndarray]
+    split: Tuple[int, int, int]
+    stride: int
+    centre: int
+
+
+def phase_diagonals(seed: int, slots: int, offsets: Sequence[int]) -> Dict[int, np.ndarray]:
+    """Diagonals with unit-modulus entries e^{i theta}, theta ~ U[0, 2 pi);
+    offsets that coincide mod slots are merged by adding their entries."""
+    g = rng(seed, 4)
+    out: Dict[int, np.ndarray] = {}
+    for d in offsets:
+        z = np.exp(1j * g.uniform(0.0, 2.0 * np.pi, slots))
+        k = int(d) % slots
+        out[k] = out[k] + z if k in out else z
+    return out
+
+
+def dft_chain(seed: int, params: Params, radix: int = 16, half: int = 7, stages: int = 4) -> List[ChainStage]:
+    """Factored DFT-like chain: stage s has diagonals at j radix^s, |j| <= half.
+
+    Stages whose offsets do not wrap use the centred progression with stride
+    radix^s, centre = 2 n1 n2 with split (2, 2, 4) (16 indices, the first one
+    empty).  When the offsets wrap modulo the slot count they are merged; the
+    distinct ones form the progression stride * t, t < count, run with the
+    smallest near-cube split holding them."""
+    S = params.slots
+    out = []
+    for s in range(stages):
+        stride = radix ** s
+        offs = [j * stride for j in range(-half, half + 1)]
+        diags = phase_diagonals(seed * 100 + s, S, offs)
+        if stride * (2 * half + 1) <= S:
+            out.append(ChainStage(diags, (2, 2, 4), stride, 8))
+        else:
+            g = math.gcd(stride, S)
+            period = S // g  # distinct multiples of stride mod S
+            ks = sorted(diags)
+            assert all(k % g == 0 for k in ks) and len(ks) <= period
+            cnt = len(ks)
+            split = (2, 2, 2) if cnt <= 8 else (2, 4, 4)
+            out.append(ChainStage(diags, split, stride, 0))
+    return out
+
+
+def chain_matvec(stages: Sequence[ChainStage], v: np.ndarray) -> np.ndarray:
+    for st in stages:
+        v = matvec(st.diags, v)
+    return v
