@@ -44,7 +44,42 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baseline (for rocprofv3)")
+    ap.add_argument("--batch-items", type=int, default=128, help="ragged batch size (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="Poisson serving run length (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--no-chain", action="store_true", help="skip the DFT-like chain")
     return ap.parse_args()
+
+
+def residue_maker(prm_n, torch, seed):
+    """Uniform residues in [0, q) per row, on the device."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+
+    def residues(moduli_rows, n=prm_n):
+        m = torch.tensor(moduli_rows, dtype=torch.int64, device="cuda").view(-1, 1)
+        x = torch.randint(0, 2 ** 62, (len(moduli_rows), n), generator=g, dtype=torch.int64, device="cuda")
+        return torch.remainder(x, m, out=x)
+    return residues
+
+
+def device_keys(prm, rots, residues):
+    kmax = prm.alpha + prm.max_level + 1
+    beta_max = -(-(prm.max_level + 1) // prm.alpha)
+    pq = list(prm.p) + list(prm.q)
+    return {r: residues(pq[:kmax] * (2 * beta_max)).view(beta_max, 2, kmax, prm.n) for r in rots}
+
+
+def events_ms(torch, stream, fn, reps):
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), time.perf_counter() - t0
 
 
 def make_inputs(P, prm, level, split, algo, seed, torch, H):
@@ -158,6 +193,214 @@ def cpu_baseline(prm, level, split):
                       "keygen/encoding excluded; decrypted max err %.1e" % (reps, err)}
 
 
+def batched_leg(P, prm, items, steps, torch, H, seed=77, chunk=32):
+    """Ragged batch: `items` ciphertexts, level ~ U{8..24}, diagonal count ~
+    U{16, 32, 64, 128} (banded), each with its own plaintexts and an
+    autotuned TH split; keys shared.  A step evaluates every item, `chunk`
+    items per ckks_lt_eval_batch call (the calls share one workspace)."""
+    import numpy as np
+    import workload as W
+    rng = np.random.Generator(np.random.PCG64([seed, 5]))
+    residues = residue_maker(prm.n, torch, seed)
+    pq = list(prm.p) + list(prm.q)
+    specs = []
+    for _ in range(items):
+        level = int(rng.integers(8, 25))
+        nd = int(rng.choice([16, 32, 64, 128]))
+        sp, _ = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, nd)
+        specs.append((level, nd, tuple(sp)))
+    rots = sorted(set().union(*[W.th_rotations(*sp) for _, _, sp in specs]))
+    keys = device_keys(prm, rots, residues)
+    delta = 2.0 ** prm.log_delta
+    batch, pt_bytes = [], 0
+    for level, nd, sp in specs:
+        K = prm.alpha + level + 1
+        qm = [prm.q[j] for j in range(level + 1)]
+        pts = [residues(pq[:K]) for _ in range(nd)]  # prefix of the PQ basis: all a level-l LT reads
+        pt_bytes += nd * K * prm.n * 8
+        batch.append(H.BatchItem(level, delta, residues(qm), residues(qm), sp, pts, delta, keys,
+                                 H.empty((level, prm.n)), H.empty((level, prm.n))))
+    chunks = [batch[i:i + chunk] for i in range(0, len(batch), chunk)]
+    wsb = max(H.ckks_lt_batch_workspace_size(P, c, H.CKKS_LT_TH_BSGS) for c in chunks)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for c in chunks:
+            code = H.ckks_lt_eval_batch(P, c, H.CKKS_LT_TH_BSGS, ws, wsb, stream)
+            assert code == H.CKKS_OK, H.strerror(code)
+
+    step()
+    ms, wall = events_ms(torch, stream, step, steps)
+    levels = [sp[0] for sp in specs]
+    res = {"items": items, "items_per_call": chunk, "steps": steps, "ms_per_batch": round(ms / steps, 3),
+           "lt_per_s": round(items * steps / wall, 1), "workspace_bytes": wsb, "resident_pt_bytes": pt_bytes,
+           "keys": len(rots), "levels": [min(levels), max(levels)],
+           "splits": sorted(set("%dx%dx%d" % sp for _, _, sp in specs)),
+           "recipe": "level ~ U{8..24}, n ~ U{16,32,64,128} banded, autotuned TH splits, shared keys, seed %d" % seed}
+    del batch, keys, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def same_shape_batch_leg(P, prm, level, split, items, steps, torch, H):
+    """`items` copies of the single-LT workload (own ciphertexts and
+    plaintexts, shared keys) in one batch."""
+    import workload as W
+    residues = residue_maker(prm.n, torch, 91)
+    pq = list(prm.p) + list(prm.q)
+    K = prm.alpha + level + 1
+    qm = [prm.q[j] for j in range(level + 1)]
+    keys = device_keys(prm, W.th_rotations(*split), residues)
+    delta = 2.0 ** prm.log_delta
+    nd = split[0] * split[1] * split[2]
+    batch = [H.BatchItem(level, delta, residues(qm), residues(qm), split, [residues(pq[:K]) for _ in range(nd)],
+                         delta, keys, H.empty((level, prm.n)), H.empty((level, prm.n))) for _ in range(items)]
+    wsb = H.ckks_lt_batch_workspace_size(P, batch, H.CKKS_LT_TH_BSGS)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        code = H.ckks_lt_eval_batch(P, batch, H.CKKS_LT_TH_BSGS, ws, wsb, stream)
+        assert code == H.CKKS_OK, H.strerror(code)
+
+    step()
+    ms, wall = events_ms(torch, stream, step, steps)
+    del batch, keys, ws
+    torch.cuda.empty_cache()
+    return {"items": items, "ms_per_batch": round(ms / steps, 3), "lt_per_s": round(items * steps / wall, 1)}
+
+
+def chain_leg(P, prm, steps, torch, H):
+    """Factored DFT-like chain: 4 sparse LTs (15 diagonals at j 16^s, the
+    last stage merged onto 8 offsets), one rescale each, level 24 -> 20."""
+    import workload as W
+    residues = residue_maker(prm.n, torch, 55)
+    pq = list(prm.p) + list(prm.q)
+    stages = W.dft_chain(3, prm)
+    rots = set()
+    for st in stages:
+        rots |= set(W.th_rotations(*st.split, stride=st.stride, centre=st.centre, slots=prm.slots))
+    keys = device_keys(prm, sorted(rots), residues)
+    kmax = prm.alpha + prm.max_level + 1
+    delta = 2.0 ** prm.log_delta
+    plan = []
+    level = 24
+    for st in stages:
+        n_idx = st.split[0] * st.split[1] * st.split[2]
+        S = prm.slots
+        present = set((st.stride * (t - st.centre)) % S for t in range(n_idx)) & set(st.diags)
+        idx = {(st.stride * (t - st.centre)) % S: t for t in range(n_idx)}
+        pts = [None] * n_idx
+        for d in present:
+            pts[idx[d]] = residues(pq[:kmax])
+        out = (H.empty((level, prm.n)), H.empty((level, prm.n)))
+        wsb = H.ckks_lt_workspace_size(P, level, st.split, pts, H.CKKS_LT_TH_BSGS, stride=st.stride, centre=st.centre)
+        plan.append((level, st, pts, out, wsb))
+        level -= 1
+    ws = torch.empty(max(p[4] for p in plan), dtype=torch.uint8, device="cuda")
+    c0 = residues([prm.q[j] for j in range(25)])
+    c1 = residues([prm.q[j] for j in range(25)])
+    stream = torch.cuda.current_stream()
+
+    def chain():
+        x0, x1, sc = c0, c1, delta
+        for level, st, pts, (o0, o1), wsb in plan:
+            _, sc = H.ckks_lt_eval(P, level, sc, x0, x1, st.split, pts, delta, keys, H.CKKS_LT_TH_BSGS, o0, o1, ws,
+                                   ws.numel(), stream, stride=st.stride, centre=st.centre)
+            x0, x1 = o0, o1
+
+    chain()
+    ms, wall = events_ms(torch, stream, chain, steps)
+    comp = 0
+    for level, st, pts, _, _ in plan:
+        K = prm.alpha + level + 1
+        beta = -(-(level + 1) // prm.alpha)
+        nk = len(W.th_rotations(*st.split, stride=st.stride, centre=st.centre, slots=prm.slots))
+        npt = sum(1 for f in pts if f is not None)
+        comp += (nk * 2 * beta * K + npt * K + 2 * (level + 1) + 2 * level) * prm.n * 8
+    del keys, plan, ws
+    torch.cuda.empty_cache()
+    return {"stages": [{"split": list(st.split), "stride": st.stride, "centre": st.centre, "diagonals": len(st.diags)}
+                       for st in stages],
+            "keys": len(rots), "ms_per_chain": round(ms / steps, 4), "chains_per_s": round(steps / wall, 2),
+            "compulsory_bytes_per_chain": comp, "effective_GB_per_s": round(comp * steps / wall / 1e9, 1)}
+
+
+def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
+    """Poisson arrivals (seeded) of single-LT requests: N ~ U{2^14, 2^15,
+    2^16}, level ~ U{8..24}, n ~ U{32..256} banded; one resident key set per N
+    (split (8,8,4), 17 rotations) and a resident pool of 256 pre-rotated
+    plaintexts per N at the top level (prefix-truncated by level and n);
+    requests admitted by the server within an HBM budget of budget_total bytes
+    (resident state included)."""
+    import numpy as np
+    import workload as W
+    split = (8, 8, 4)
+    rings, resident = [], 0
+    for log_n in (14, 15, 16):
+        prm = W.params_n16(log_n=log_n)
+        P = H.ckks_params_create(prm.log_n, prm.q, prm.p, prm.dnum)
+        residues = residue_maker(prm.n, torch, seed + log_n)
+        pq = list(prm.p) + list(prm.q)
+        kmax = prm.alpha + prm.max_level + 1
+        keys = device_keys(prm, W.th_rotations(*split), residues)
+        pool = [residues(pq[:kmax]) for _ in range(256)]
+        cts = [(residues(list(prm.q)), residues(list(prm.q))) for _ in range(4)]
+        resident += sum(k.numel() * 8 for k in keys.values()) + 256 * kmax * prm.n * 8 + 4 * 2 * 25 * prm.n * 8
+        rings.append((prm, P, keys, pool, cts))
+    rng = np.random.Generator(np.random.PCG64([seed, 6]))
+    nreq = int(seconds * rate)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs = []
+    out_bytes = 0
+    for i in range(nreq):
+        g = int(rng.integers(0, 3))
+        level = int(rng.integers(8, 25))
+        nd = int(rng.integers(32, 257))
+        prm = rings[g][0]
+        reqs.append((float(arrivals[i]), g, level, nd, int(rng.integers(0, 4)),
+                     (H.empty((level, prm.n)), H.empty((level, prm.n)))))
+        out_bytes += 2 * level * prm.n * 8
+    resident += out_bytes
+    free, _ = torch.cuda.mem_get_info()
+    arena = int(min(budget_total - resident, free - (8 << 30)))
+    torch.cuda.synchronize()
+
+    def run(burst):
+        with H.Server(arena, max_batch=8, max_inflight=2) as S:
+            rid = [H.ckks_server_add_ring(S, r[1], r[2]) for r in rings]
+            t0 = time.perf_counter()
+            for at, g, level, nd, ci, (o0, o1) in (reqs[:burst] if burst else reqs):
+                if not burst:
+                    dt = at - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                prm, P, keys, pool, cts = rings[g]
+                c0, c1 = cts[ci]
+                H.ckks_server_submit(S, rid[g], level, 2.0 ** prm.log_delta, c0, c1, split, pool[:nd],
+                                     2.0 ** prm.log_delta, o0, o1)
+            H.ckks_server_wait_all(S)
+            wall = time.perf_counter() - t0
+            st = H.ckks_server_stats(S)
+        return st, wall
+
+    st, wall = run(0)
+    stb, wallb = run(min(nreq, 400))
+    res = {"requests": nreq, "rate_req_per_s": rate, "seconds": seconds, "completed": st["completed"],
+           "failed": st["failed"], "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
+           "mean_ms": round(st["mean_s"] * 1e3, 2), "lt_per_s": round(st["completed"] / max(st["span_s"], 1e-9), 1),
+           "batches": st["batches"], "max_batch": st["max_batch"], "max_inflight": st["max_inflight"],
+           "arena_bytes": arena, "arena_peak_bytes": st["arena_peak"], "resident_bytes": resident,
+           "burst": {"requests": min(nreq, 400), "lt_per_s": round(stb["completed"] / max(stb["span_s"], 1e-9), 1),
+                     "p50_ms": round(stb["p50_s"] * 1e3, 2), "p99_ms": round(stb["p99_s"] * 1e3, 2)},
+           "recipe": "Poisson %.0f req/s, N ~ U{2^14,2^15,2^16}, level ~ U{8..24}, n ~ U{32..256}, split (8,8,4), "
+                     "seed %d; max_batch 8, 2 streams" % (rate, seed)}
+    del rings, reqs
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -226,6 +469,20 @@ def main():
         "roofline": roofline,
         "kernels": breakdown,
     }
+    print("single-LT legs done", flush=True, file=sys.stderr)
+    same = same_shape_batch_leg(P, prm, level, th_split, 32, 5, torch, H)
+    same["vs_plain_bsgs"] = round(same["lt_per_s"] / (1e3 / bs_ms), 3)
+    out["batched_same_shape"] = same
+    if args.batch_items > 0:
+        b = batched_leg(P, prm, args.batch_items, 3, torch, H)
+        out["batched_ragged"] = b
+        print("batched legs done", flush=True, file=sys.stderr)
+    if not args.no_chain:
+        out["dft_chain"] = chain_leg(P, prm, 10, torch, H)
+        print("chain leg done", flush=True, file=sys.stderr)
+    if args.serve_seconds > 0:
+        out["serving"] = serving_leg(args.serve_seconds, args.serve_rate, torch, H)
+        print("serving leg done", flush=True, file=sys.stderr)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prm, level, th_split)
     print(json.dumps(out), flush=True)

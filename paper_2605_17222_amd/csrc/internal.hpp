@@ -27,6 +27,8 @@ struct PrimeDev {
   uint64_t pmod, pmod_sh;  // P mod q (0 on the special primes) and companion
   const uint64_t* tw;      // [4][N]: psi^br(i), Shoup, psi^-br(i), Shoup (integer primes) or
                            // the same powers as doubles and each divided by q (fp primes)
+  const double* trow;      // fp primes: row-pass twiddle factors, [2][row_tables_size] (forward,
+                           // inverse); see ntt_row_tables_size
   int fp;                  // q < 2^46: NTT butterflies in exact FP64 arithmetic
   int pad;
   double qd, qinv_d;       // q and 1/q as doubles
@@ -34,6 +36,22 @@ struct PrimeDev {
 };
 
 constexpr uint64_t kFpPrimeLimit = 1ull << 46;
+
+// The two NTT passes split log2 N = (log2 N - B) + B: the column pass does the
+// first log2 N - B stages, the row pass the last B.
+__host__ __device__ inline int ntt_row_log(int log_n) { return log_n / 2; }
+
+// Row-pass twiddles factor (fp primes): stage s (0 <= s < B) of row `row` uses
+// rho^br(2^(log N - B + s) + row 2^s + y), y < 2^s, with rho = psi or psi^-1
+// and br over log2 N bits; it equals G[2^s + y] * R[row][s] mod q with
+//   G[2^s + y] = rho^(2^(B-1-s) + br_s(y) 2^(log N - s)),
+//   R[row][s]  = rho^(br_(log N - B)(row) 2^(B - s)).
+// Per direction: G (2^B doubles), then R as (value, value / q) pairs for each
+// (row, s): 2^B + 2 * 2^(log N - B) * B doubles.
+__host__ __device__ inline size_t ntt_row_tables_size(int log_n) {
+  const int B = ntt_row_log(log_n);
+  return ((size_t)1 << B) + 2 * ((size_t)1 << (log_n - B)) * B;
+}
 
 // Basis conversion eq. (3) from `ns` source limbs to `nd` destination limbs,
 // plus the final factor S^-1 of a division step (eq. (4), eq. (1)).
@@ -164,6 +182,7 @@ struct ckks_params {
   std::vector<uint64_t> primes;        // PQ order
   ckks::PrimeDev* d_primes = nullptr;  // device [K_max]
   uint64_t* d_tw = nullptr;            // device [K_max][4][N]
+  double* d_trow = nullptr;            // device [K_max][2][ntt_row_tables_size]
   ckks::BConvPlan* d_plans = nullptr;  // device plan table
   std::vector<int> plan_decomp;        // level * beta_max + b -> plan index
   std::vector<int> plan_moddown, plan_mdrescale, plan_rescale;  // per level

@@ -106,6 +106,39 @@ int make_plan(const std::vector<uint64_t>& pr, const std::vector<int>& src, cons
   return CKKS_OK;
 }
 
+double as_double(uint64_t x) { return (double)x; }
+
+// Row-pass twiddle factors of one prime and direction (root rho = psi or
+// psi^-1); layout as in ntt_row_tables_size.  Returns false if a product
+// G * R differs from the full table `full` (rho^br(i) for i < N), which is
+// checked for every entry the row pass uses.
+bool row_tables(uint64_t q, uint64_t rho, int log_n, const uint64_t* full, double* out) {
+  const int B = ntt_row_log(log_n), L1 = log_n - B;
+  const uint64_t n = 1ull << log_n, two_n = 2 * n;
+  const size_t rows = (size_t)1 << L1;
+  std::vector<uint64_t> G((size_t)1 << B, 0), R(rows * B);
+  for (int s = 0; s < B; ++s)
+    for (uint32_t y = 0; y < (1u << s); ++y) {
+      const uint64_t e = ((1ull << (B - 1 - s)) + (uint64_t)brev(y, s) * (n >> s)) % two_n;
+      G[(1u << s) + y] = pw(rho, e, q);
+    }
+  for (size_t row = 0; row < rows; ++row)
+    for (int s = 0; s < B; ++s) R[row * B + s] = pw(rho, ((uint64_t)brev((uint32_t)row, L1) << (B - s)) % two_n, q);
+  for (size_t row = 0; row < rows; ++row)
+    for (int s = 0; s < B; ++s)
+      for (uint32_t y = 0; y < (1u << s); ++y) {
+        const size_t i = ((size_t)1 << (L1 + s)) + row * ((size_t)1 << s) + y;
+        if (mm(G[(1u << s) + y], R[row * B + s], q) != full[i]) return false;
+      }
+  for (size_t k = 0; k < G.size(); ++k) out[k] = as_double(G[k]);
+  double* r = out + G.size();
+  for (size_t k = 0; k < R.size(); ++k) {
+    r[2 * k] = as_double(R[k]);
+    r[2 * k + 1] = as_double(R[k]) / (double)q;
+  }
+  return true;
+}
+
 }  // namespace
 
 int params_create(const ckks_params_desc* d, ckks_params** out) {
@@ -135,6 +168,8 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
 
   // psi and twiddle tables.
   std::vector<uint64_t> tw((size_t)K * 4 * n);
+  const size_t rts = ntt_row_tables_size(P->log_n);
+  std::vector<double> trow((size_t)K * 2 * rts, 0.0);
   std::vector<PrimeDev> pd(K);
   for (int i = 0; i < K; ++i) {
     const uint64_t q = P->primes[i];
@@ -158,6 +193,17 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
       b = mm(b, psi_inv, q);
     }
     const bool fp = q < kFpPrimeLimit;
+    if (fp) {
+      std::vector<uint64_t> full_f(n), full_i(n);
+      for (int k = 0; k < n; ++k) {
+        const uint32_t r = brev(k, P->log_n);
+        full_f[k] = pf[r];
+        full_i[k] = pi[r];
+      }
+      double* tr = trow.data() + (size_t)i * 2 * rts;
+      if (!row_tables(q, psi, P->log_n, full_f.data(), tr) || !row_tables(q, psi_inv, P->log_n, full_i.data(), tr + rts))
+        return CKKS_E_UNSUPPORTED;  // internal consistency check of the factorisation
+    }
     auto dbits = [](double x) {
       uint64_t u;
       memcpy(&u, &x, 8);
@@ -242,10 +288,15 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
 
   // Upload.
   if (hipMalloc(&P->d_tw, tw.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
+  if (hipMalloc(&P->d_trow, trow.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_primes, pd.size() * sizeof(PrimeDev)) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_plans, plans.size() * sizeof(BConvPlan)) != hipSuccess) return CKKS_E_NOMEM;
-  for (int i = 0; i < K; ++i) pd[i].tw = P->d_tw + (size_t)i * 4 * n;
+  for (int i = 0; i < K; ++i) {
+    pd[i].tw = P->d_tw + (size_t)i * 4 * n;
+    pd[i].trow = P->d_trow + (size_t)i * 2 * rts;
+  }
   if (hipMemcpy(P->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return CKKS_E_DEVICE;
+  if (hipMemcpy(P->d_trow, trow.data(), trow.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return CKKS_E_DEVICE;
   if (hipMemcpy(P->d_primes, pd.data(), pd.size() * sizeof(PrimeDev), hipMemcpyHostToDevice) != hipSuccess)
     return CKKS_E_DEVICE;
   if (hipMemcpy(P->d_plans, plans.data(), plans.size() * sizeof(BConvPlan), hipMemcpyHostToDevice) != hipSuccess)
@@ -260,6 +311,7 @@ void params_destroy(ckks_params* P) {
   if (hipGetDevice(&cur) != hipSuccess) cur = -1;
   if (cur != P->device) (void)hipSetDevice(P->device);
   if (P->d_tw) (void)hipFree(P->d_tw);
+  if (P->d_trow) (void)hipFree(P->d_trow);
   if (P->d_primes) (void)hipFree(P->d_primes);
   if (P->d_plans) (void)hipFree(P->d_plans);
   if (cur >= 0 && cur != P->device) (void)hipSetDevice(cur);
