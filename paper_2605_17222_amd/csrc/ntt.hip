@@ -29,7 +29,12 @@
 //
 // Stage s of a sub-transform of P = 2^p points whose global twiddle base is B
 // uses twiddle index B 2^s + (x >> (p - s)) for butterfly position x; B = 1
-// for the column pass and B = N1 + row for the row pass.
+// for the column pass and B = N1 + row for the row pass.  The column pass
+// reads its 2^p - 1 twiddles from the full table (shared by all columns, so
+// they stay in cache); the row pass of an FP64 limb would read a different
+// 2^p - 1 for every row (the whole table, twice the limb's own bytes), so it
+// forms them instead as G[s][y] R[row][s] mod q from two small tables (the
+// factorisation is described at ntt_row_tables_size).
 #include "internal.hpp"
 #include "modarith.hpp"
 
@@ -73,10 +78,33 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   uint64_t v[16];  // integer residues, or double bits on the FP path
   auto addr = [&](int x) -> size_t { return COL ? (size_t)x * ncols + sub : (size_t)sub * P + x; };
 
-  // One butterfly between registers u and u + d with twiddle index ti.
-  auto bfly = [&](int u, int d, uint32_t ti) {
+  // FP row pass: the factor tables of this direction and this row.
+  const double* __restrict__ tg = nullptr;
+  const double* __restrict__ tr = nullptr;
+  if (FP && !COL) {
+    tg = pr.trow + (FWD ? 0 : ntt_row_tables_size(log_n));
+    tr = tg + P + 2 * (size_t)sub * PLOG;
+  }
+  // Twiddle of stage s, group y (index base 2^s + y): the value and its
+  // companion (Shoup word, or w/q on the FP path), as raw 64-bit words.
+  auto twid = [&](int s, uint32_t y, uint64_t& w, uint64_t& wp) {
+    if (FP && !COL) {
+      // |w| <= 0.75 q; wq = w/q to within 2 ulp, which keeps the products
+      // that use it within the bounds of fp_mulmod.
+      const double wv = fp_mulmod(tg[(1u << s) + y], tr[2 * s], tr[2 * s + 1], qd);
+      w = as_u(wv);
+      wp = as_u(wv * qi);
+    } else {
+      const uint32_t ti = (base << s) + y;
+      w = tw[ti];
+      wp = tw[n + ti];
+    }
+  };
+
+  // One butterfly between registers u and u + d with twiddle (tw_w, tw_p).
+  auto bfly = [&](int u, int d, uint64_t tw_w, uint64_t tw_p) {
     if (FP) {
-      const double w = as_d(tw[ti]), wq = as_d(tw[n + ti]);
+      const double w = as_d(tw_w), wq = as_d(tw_p);
       const double X = as_d(v[u]), Y = as_d(v[u + d]);
       if (FWD) {
         const double r = fp_mulmod(Y, w, wq, qd);
@@ -87,7 +115,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
         v[u + d] = as_u(fp_mulmod(X - Y, w, wq, qd));
       }
     } else {
-      const uint64_t w = tw[ti], wp = tw[n + ti];
+      const uint64_t w = tw_w, wp = tw_p;
       if (FWD) {
         uint64_t X = v[u];
         X = X >= q2 ? X - q2 : X;
@@ -103,26 +131,35 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
       }
     }
   };
-  // Stages 0..3 in layout "x = j + T u" (twiddle index depends on u only).
+  // Stages 0..3 in layout "x = j + T u": group y = u >> (4 - s), 2^s groups.
   auto round1 = [&]() {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int s = FWD ? k : 3 - k;
       const int d = 8 >> s;
+      uint64_t W[8], WP[8];
+#pragma unroll
+      for (int y = 0; y < (1 << s); ++y) twid(s, (uint32_t)y, W[y], WP[y]);
 #pragma unroll
       for (int u = 0; u < 16; ++u)
-        if (!(u & d)) bfly(u, d, (base << s) + (uint32_t)(u >> (4 - s)));
+        if (!(u & d)) bfly(u, d, W[u >> (4 - s)], WP[u >> (4 - s)]);
     }
   };
-  // Stages 4..PLOG-1 in layout "x = 16 j + u".
+  // Stages 4..PLOG-1 in layout "x = 16 j + u": group (16 j + u) >> sh with
+  // sh = PLOG - s <= 4, i.e. (16 j >> sh) + (u >> sh), 16 >> sh groups.
   auto round2 = [&]() {
 #pragma unroll
     for (int k = 4; k < PLOG; ++k) {
       const int s = FWD ? k : PLOG - 1 - (k - 4);
       const int d = P >> (s + 1);
+      const int sh = PLOG - s;
+      const uint32_t y0 = (uint32_t)(16 * j) >> sh;
+      uint64_t W[8], WP[8];
+#pragma unroll
+      for (int c = 0; c < (16 >> sh); ++c) twid(s, y0 + (uint32_t)c, W[c], WP[c]);
 #pragma unroll
       for (int u = 0; u < 16; ++u)
-        if (!(u & d)) bfly(u, d, (base << s) + (uint32_t)((16 * j + u) >> (PLOG - s)));
+        if (!(u & d)) bfly(u, d, W[u >> sh], WP[u >> sh]);
     }
   };
   auto recentre = [&]() {
