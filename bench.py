@@ -469,6 +469,13 @@ def main():
         "roofline": roofline,
         "kernels": breakdown,
     }
+    # the split the library's autotuner picks for this workload, timed the same way
+    at_split, at_pred = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, 64)
+    at_split = tuple(at_split)
+    wall_a, ms_a, _, _ = time_lt(P, prm, level, at_split, "th", args.steps, 2, torch, H)
+    out["autotuned_split"] = {"split": list(at_split), "predicted_ms": round(at_pred * 1e3, 4),
+                              "ms_per_lt": round(ms_a / args.steps, 4), "lt_per_s": round(args.steps / wall_a, 2),
+                              "compulsory_bytes_per_lt": compulsory_bytes(prm, level, at_split, "th")}
     print("single-LT legs done", flush=True, file=sys.stderr)
     same = same_shape_batch_leg(P, prm, level, th_split, 32, 5, torch, H)
     same["vs_plain_bsgs"] = round(same["lt_per_s"] / (1e3 / bs_ms), 3)

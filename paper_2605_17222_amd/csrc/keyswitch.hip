@@ -24,6 +24,11 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Operands read once per launch (keys, digits, plaintexts, products) are
+// loaded with the non-temporal hint: they stream through without displacing
+// cached data, which lifts the achieved read bandwidth on gfx950.
+__device__ __forceinline__ uint64_t ld_nt(const uint64_t* p) { return __builtin_nontemporal_load(p); }
+
 template <int NDIG>
 __global__ void __launch_bounds__(kThreads)
     ks_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
@@ -40,12 +45,12 @@ __global__ void __launch_bounds__(kThreads)
     if (l >= a.K[i]) continue;  // this digit set's level has fewer limbs
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b)
-      if (b < a.beta[i]) d[i][b] = a.digits[i][((size_t)b * a.K[i] + l) * n + p];
+      if (b < a.beta[i]) d[i][b] = ld_nt(a.digits[i] + ((size_t)b * a.K[i] + l) * n + p);
     if (a.add[i]) {
       if (a.add_pscaled[i])
-        addv[i] = (l < alpha) ? 0 : shoup(a.add[i][(size_t)(l - alpha) * n + p], pr.pmod, pr.pmod_sh, q);
+        addv[i] = (l < alpha) ? 0 : shoup(ld_nt(a.add[i] + (size_t)(l - alpha) * n + p), pr.pmod, pr.pmod_sh, q);
       else
-        addv[i] = a.add[i][(size_t)l * n + p];
+        addv[i] = ld_nt(a.add[i] + (size_t)l * n + p);
     }
   }
   for (int k = 0; k < a.nkeys; ++k) {
@@ -54,8 +59,8 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b) {
       if (b < a.kbeta) {
-        k0[b] = key[(((size_t)b * 2 + 0) * a.kmax + l) * n + p];
-        k1[b] = key[(((size_t)b * 2 + 1) * a.kmax + l) * n + p];
+        k0[b] = ld_nt(key + (((size_t)b * 2 + 0) * a.kmax + l) * n + p);
+        k1[b] = ld_nt(key + (((size_t)b * 2 + 1) * a.kmax + l) * n + p);
       }
     }
     const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
@@ -102,12 +107,12 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b) {
       if (b < a.beta) {
-        const uint64_t d = dg[(size_t)b * a.K * n + s];
-        add128(x, mul_wide(d, key[((size_t)b * 2 + 0) * a.kmax * n + s]));
-        add128(y, mul_wide(d, key[((size_t)b * 2 + 1) * a.kmax * n + s]));
+        const uint64_t d = ld_nt(dg + (size_t)b * a.K * n + s);
+        add128(x, mul_wide(d, ld_nt(key + ((size_t)b * 2 + 0) * a.kmax * n + s)));
+        add128(y, mul_wide(d, ld_nt(key + ((size_t)b * 2 + 1) * a.kmax * n + s)));
       }
     }
-    c0 = add_mod(c0, add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), a.add[k][s], q), q);
+    c0 = add_mod(c0, add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), ld_nt(a.add[k] + s), q), q);
     c1 = add_mod(c1, barrett128(y, q, pr.r_lo, pr.r_hi), q);
   }
   a.c0[o] = c0;
@@ -136,17 +141,17 @@ __global__ void __launch_bounds__(kThreads)
     if (m == 0 && a.pscaled0) {
       // (a_0, b_0) = (P c0', P c1'): zero on the special primes.
       const int lq = l + a.prime_off - alpha;
-      av = lq < 0 ? 0 : shoup(a.a[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
-      bv = lq < 0 ? 0 : shoup(a.b[0][(size_t)lq * n + p], pr.pmod, pr.pmod_sh, q);
+      av = lq < 0 ? 0 : shoup(ld_nt(a.a[0] + (size_t)lq * n + p), pr.pmod, pr.pmod_sh, q);
+      bv = lq < 0 ? 0 : shoup(ld_nt(a.b[0] + (size_t)lq * n + p), pr.pmod, pr.pmod_sh, q);
     } else {
-      av = a.a[m][off];
-      bv = a.b[m][off];
+      av = ld_nt(a.a[m] + off);
+      bv = ld_nt(a.b[m] + off);
     }
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const uint64_t* __restrict__ fp = a.f[k][m];
       if (fp) {
-        const uint64_t f = fp[off];
+        const uint64_t f = ld_nt(fp + off);
         add128(x[k], mul_wide(av, f));
         add128(y[k], mul_wide(bv, f));
       }

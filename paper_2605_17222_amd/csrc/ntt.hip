@@ -192,7 +192,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
 
   if (FWD) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = src[addr(j + T * u)];
+    for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(src + addr(j + T * u));
     if (first) convert_in();
     round1();
     recentre();
@@ -219,17 +219,17 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
       for (int u = 0; u < 16; ++u) {
         const int x = j + T * u;
         uint64_t y = canon(v[u]);
-        if (epi == EPI_SUBMUL) y = shoup(aux[addr(x)] - y + q, c, cs, q);
+        if (epi == EPI_SUBMUL) y = shoup(__builtin_nontemporal_load(aux + addr(x)) - y + q, c, cs, q);
         dst[addr(x)] = y;
       }
     }
   } else {
     if (COL) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = src[addr(16 * j + u)];
+      for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(src + addr(16 * j + u));
     } else {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = src[addr(j + T * u)];
+      for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(src + addr(j + T * u));
       if (R.copy) {
         uint64_t* __restrict__ cp = R.copy + (size_t)limb * n;
 #pragma unroll
