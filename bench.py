@@ -34,7 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # (KiB per dispatch) scaled by what the counters read for a plain 256 MiB copy
 # kernel (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see profiles/.  None once the
 # kernel has changed since the counters were taken.
-TRAFFIC = {}
+TRAFFIC = {
+    # mac_kernel<4> at N=2^16, level 24, TH-BSGS (4,4,4): (2 x 831084.0 + 139264.0) KiB
+    "ptmac": (2 * 831084.0 + 139264.0) * 1024,
+}
 
 
 def parse():
@@ -447,7 +450,7 @@ def main():
     n_l, ms_l, bytes_l = prof_dom[dom]
     achieved = bytes_l / (ms_l * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(dom),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(dom), "traffic_unit": "bytes/launch",
                 "launches_per_step": n_l / args.steps, "avg_launch_us": round(ms_l / n_l * 1e3, 2),
                 "algorithmic_bytes_per_launch": round(bytes_l / n_l), "share_of_step": round(ms_l / ms_ev, 3)}
     breakdown = {k: {"launches_per_step": v[0] / probe_steps, "ms_per_step": round(v[1] / probe_steps, 4),
