@@ -118,11 +118,20 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built.
+
+    torch is imported first: its wheel carries its own HIP runtime, and the
+    library's HIP calls must bind to that same runtime (loaded first, it
+    serves both), or the process would start two runtimes on one device and
+    torch's tensors and streams would belong to the other one."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libckks_lt.so is not built (run paper_2605_17222_amd/build.py)")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         L.ckks_strerror.restype = ctypes.c_char_p
         L.ckks_strerror.argtypes = [ctypes.c_int]

@@ -89,3 +89,21 @@ def test_batch_bad_item_is_skipped():
     assert good.status == H.CKKS_OK and bad.status == H.CKKS_E_INVALID_ARG
     ref = o.lt_th(2, it["ct"], (2, 2, 4), it["pts"], keys)
     assert np.array_equal(np.stack([H.to_host(good.out0), H.to_host(good.out1)]), ref)
+
+
+def test_batch_n16_autotuned_splits():
+    # The batched benchmark's launch configuration: splits chosen by the
+    # library's autotuner for each (level, n), several levels in one call.
+    prm = W.params_n16()
+    specs = []
+    for level, nd in [(24, 64), (16, 128), (9, 32)]:
+        sp, _ = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, nd)
+        specs.append((level, nd, tuple(sp)))
+    log("autotuned splits", specs)
+    o, keys, items, delta = _batch_case(prm, specs, 5)
+    got = _run_gpu(prm, keys, items, delta)
+    for it, (g, lvl, sc) in zip(items, got):
+        ref = o.lt_th(it["level"], it["ct"], it["split"], it["pts"], keys)
+        assert np.array_equal(g, ref), it["split"]
+        z = o.decrypt_slots(g, sc)
+        assert np.abs(z - W.matvec(it["diags"], it["v"])).max() <= 1e-4

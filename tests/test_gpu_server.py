@@ -103,3 +103,14 @@ def test_server_two_rings_n15_n16():
     alone, _ = _serve([r15, r16], order, 4 << 30, max_batch=1, max_inflight=1)
     for key in mix:
         assert np.array_equal(mix[key][0], alone[key][0])
+
+
+def test_server_serving_split_n14():
+    # The serving configuration's resident split (8, 8, 4) with up to 256
+    # diagonals, N = 2^14, requests of different levels and diagonal counts.
+    r14 = Ring(W.params_n16(log_n=14), [(24, 256, (8, 8, 4)), (8, 40, (8, 8, 4)), (15, 200, (8, 8, 4))], 41)
+    order = [(0, 0), (0, 1), (0, 2)]
+    log("n14 serving split")
+    mix, st = _serve([r14], order, 8 << 30, max_batch=4, max_inflight=2)
+    assert st["completed"] == 3
+    _check([r14], mix, 1e-4)
