@@ -379,19 +379,29 @@ typedef struct {
 int ckks_lt_cost_model(int log_n, int level, int alpha, int algo, int n1, int n2, int n3, int word_bits,
                  ckks_lt_cost* out);
 
-/* Device rates the autotuner predicts with (NULL: values measured on MI355X). */
+/* Device rates the predictor uses (NULL: values fitted on MI355X). */
 typedef struct {
   double ntt_limb_s;        /* seconds per limb NTT (both passes) at N = 2^16   */
   double bconv_product_s;   /* seconds per basis-conversion product            */
   double hbm_bytes_per_s;   /* achieved bandwidth of the HBM-bound kernels     */
+  double layer_s;           /* latency per active hoisting layer (a chain of
+                               dependent launches)                            */
 } ckks_lt_rates;
 
 /*
+ * Predicted device seconds of one LT with this split and n_diag present
+ * diagonals: the operation counts of ckks_lt_cost_model priced with `rates`,
+ * plus the words the key-switch and MAC kernels move as this library
+ * schedules them.  DH-BSGS (n1, n2) is priced as TH-BSGS (1, n1, n2).
+ */
+int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, int n3, int n_diag,
+                    const ckks_lt_rates* rates, double* seconds);
+
+/*
  * Chooses the split for a banded LT with diagonal offsets 0 .. n_diag-1 that
- * minimises the predicted device time, among splits with n1 n2 n3 in
- * [n_diag, 2 n_diag) (padding with absent diagonals) needing at most max_keys
- * switching keys (max_keys <= 0: no limit).  Writes the split and the
- * predicted seconds.
+ * minimises ckks_lt_predict, among splits with n1 n2 n3 in [n_diag, 2 n_diag)
+ * (padding with absent diagonals) needing at most max_keys switching keys
+ * (max_keys <= 0: no limit).  Writes the split and the predicted seconds.
  */
 int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int max_keys, const ckks_lt_rates* rates,
                      int* n1, int* n2, int* n3, double* predicted_s);

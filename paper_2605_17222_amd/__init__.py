@@ -37,13 +37,12 @@ CKKS_LT_TH_BSGS = 2
 CKKS_LT_DH_BSGS = 3
 
 EXPORTED = [
-    "ckks_strerror", "ckks_params_create", "ckks_params_destroy", "ckks_params_info",
-    "ckks_lt_workspace_size", "ckks_lt_eval", "ckks_op_ntt", "ckks_op_decompose", "ckks_op_moddown",
-    "ckks_op_rescale", "ckks_op_workspace_size", "ckks_op_keyswitch", "ckks_op_automorph",
-    "ckks_profile_enable", "ckks_profile_read", "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch",
-    "ckks_lt_cost_model", "ckks_lt_autotune", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit",
-    "ckks_server_poll", "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats",
-    "ckks_server_destroy",
+    "ckks_strerror", "ckks_params_create", "ckks_params_destroy", "ckks_params_info", "ckks_lt_workspace_size",
+    "ckks_lt_eval", "ckks_op_ntt", "ckks_op_decompose", "ckks_op_moddown", "ckks_op_rescale",
+    "ckks_op_workspace_size", "ckks_op_keyswitch", "ckks_op_automorph", "ckks_profile_enable", "ckks_profile_read",
+    "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch", "ckks_lt_cost_model", "ckks_lt_autotune",
+    "ckks_lt_predict", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit", "ckks_server_poll",
+    "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats", "ckks_server_destroy",
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
@@ -88,7 +87,7 @@ class LtCost(ctypes.Structure):
 
 class LtRates(ctypes.Structure):
     _fields_ = [("ntt_limb_s", ctypes.c_double), ("bconv_product_s", ctypes.c_double),
-                ("hbm_bytes_per_s", ctypes.c_double)]
+                ("hbm_bytes_per_s", ctypes.c_double), ("layer_s", ctypes.c_double)]
 
 
 class LtItem(ctypes.Structure):
@@ -167,6 +166,7 @@ def lib() -> ctypes.CDLL:
         L.ckks_lt_eval_batch.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(LtItem), ctypes.c_int,
                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.ckks_lt_cost_model.argtypes = [ctypes.c_int] * 8 + [ctypes.POINTER(LtCost)]
+        L.ckks_lt_predict.argtypes = [ctypes.c_int] * 8 + [ctypes.POINTER(LtRates), ctypes.POINTER(ctypes.c_double)]
         L.ckks_lt_autotune.argtypes = [ctypes.c_int] * 6 + [ctypes.POINTER(LtRates)] + \
             [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)]
         L.ckks_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
@@ -433,8 +433,19 @@ def ckks_lt_cost_model(log_n: int, level: int, alpha: int, algo: int, split: Seq
     return {f: getattr(c, f) for f, _ in LtCost._fields_}
 
 
+def ckks_lt_predict(log_n: int, level: int, alpha: int, algo: int, split: Sequence[int], n_diag: int,
+                    rates: Optional[Tuple[float, float, float, float]] = None) -> float:
+    """Predicted device seconds of one LT (the library's model)."""
+    n1, n2, n3 = (list(split) + [1, 1])[:3]
+    t = ctypes.c_double()
+    r = ctypes.byref(LtRates(*rates)) if rates else None
+    _check(lib().ckks_lt_predict(log_n, level, alpha, algo, n1, n2, n3, n_diag, r, ctypes.byref(t)),
+           "ckks_lt_predict")
+    return t.value
+
+
 def ckks_lt_autotune(log_n: int, level: int, alpha: int, algo: int, n_diag: int, max_keys: int = 0,
-                     rates: Optional[Tuple[float, float, float]] = None):
+                     rates: Optional[Tuple[float, float, float, float]] = None):
     """(split, predicted seconds) chosen by the library's cost model."""
     a, b, c, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     r = ctypes.byref(LtRates(*rates)) if rates else None

@@ -12,10 +12,12 @@
 // N = 2^16, L+1 = 32, alpha = 12 this gives Table II's switching-key sizes
 // exactly and its DH-BSGS / TH-BSGS multiplication counts within 0.5%.
 //
-// The autotuner predicts a split's time on the device from the same counts:
+// The predictor estimates a split's time on the device from the same counts:
 // limb NTTs x (time per limb NTT) + conversion products x (time per product)
-// + key-switch and plaintext-MAC bytes / (achieved HBM bandwidth), and picks
-// the fastest split that needs at most max_keys switching keys.
+// + the words the key-switch and MAC kernels move (as this library schedules
+// them) / (achieved bandwidth) + a latency per active hoisting layer (each
+// layer is a chain of dependent launches).  The autotuner picks the split
+// with the smallest prediction that needs at most max_keys switching keys.
 #include <math.h>
 #include <string.h>
 
@@ -98,20 +100,77 @@ int ckks_lt_cost_model(int log_n, int level, int alpha, int algo, int n1, int n2
   return CKKS_OK;
 }
 
-int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int max_keys, const ckks_lt_rates* rates,
-                     int* n1, int* n2, int* n3, double* predicted_s) {
-  if (!n1 || !n2 || !n3 || n_diag < 1 || log_n < 1 || log_n > 20) return CKKS_E_INVALID_ARG;
+int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, int n3, int n_diag,
+                    const ckks_lt_rates* rates, double* seconds) {
+  if (!seconds || n_diag < 0 || log_n < 1 || log_n > 20 || level < 0 || alpha < 1 || n1 < 1 || n2 < 1 || n3 < 1)
+    return CKKS_E_INVALID_ARG;
   ckks_lt_rates r;
   if (rates) {
     r = *rates;
   } else {
-    // Measured on one MI355X at N = 2^16 (two-pass NTT, limb-batched launches).
-    r.ntt_limb_s = 0.77e-6;
-    r.bconv_product_s = 0.76e-12;
-    r.hbm_bytes_per_s = 5.0e12;
+    // Fitted on one MI355X at N = 2^16 (levels 8..24, 16..511 diagonals,
+    // 120 splits; mean prediction error 7%): BConv from its own kernel time.
+    r.ntt_limb_s = 4.19e-7;
+    r.bconv_product_s = 0.77e-12;
+    r.hbm_bytes_per_s = 4.06e12;
+    r.layer_s = 45e-6;
   }
-  const double nscale = (double)(1 << log_n) * log_n / (65536.0 * 16);
+  if (algo == CKKS_LT_DH_BSGS) {  // Algorithm 2 with an empty inner layer
+    n3 = n2;
+    n2 = n1;
+    n1 = 1;
+    algo = CKKS_LT_TH_BSGS;
+  }
+  if (algo != CKKS_LT_TH_BSGS) n3 = 1;
+  ckks_lt_cost c;
+  const int e = ckks_lt_cost_model(log_n, level, alpha, algo, n1, n2, n3, 64, &c);
+  if (e != CKKS_OK) return e;
+  const double N = (double)(1 << log_n);
+  const double nscale = N * log_n / (65536.0 * 16);
   const int Lq = level + 1, K = alpha + Lq, beta = (Lq + alpha - 1) / alpha;
+  double conv = 0;
+  for (int g = 0; g < beta; ++g) {
+    const int gs = std::min(alpha, Lq - alpha * g);
+    conv += (double)gs * (K - gs);
+  }
+  const double bconv_products = (c.decompose * conv + c.moddown * alpha * Lq) * N;
+  // Words moved per coefficient position by the HBM-bound kernels as this
+  // library schedules them: a key (2 beta K words at this level) is read
+  // once per launch for every digit set that uses it (up to 8 digit sets per
+  // launch); every product is written once and read once by the MAC.
+  const double keyw = 2.0 * beta * K;
+  double words = 0;
+  int layers = 0;
+  if (algo == CKKS_LT_TH_BSGS) {
+    if (n1 > 1) {
+      words += beta * K + (n1 - 1) * keyw + (n1 - 1) * 2.0 * K + Lq;
+      ++layers;
+    }
+    if (n2 > 1) {
+      words += ((n1 + 7) / 8) * (n2 - 1) * keyw + n1 * (double)beta * K + n1 * (double)K +
+               (double)n1 * (n2 - 1) * 2.0 * K;
+      ++layers;
+    }
+    words += 2.0 * n1 * n2 * K + (double)n_diag * K + 2.0 * n3 * K;
+    if (n3 > 1) {
+      words += (n3 - 1) * (beta * (double)K + keyw + K) + 4.0 * K;
+      ++layers;
+    }
+  } else {
+    // plain BSGS: every rotation has its own digits, key, (x, y), ModDown
+    // and automorphism; the plaintext products are at the Q basis.
+    words += (n1 - 1 + n2 - 1) * (beta * (double)K + keyw + 2.0 * K + 5.0 * Lq);
+    words += 2.0 * n1 * Lq + (double)n_diag * Lq + 2.0 * n2 * Lq;
+    layers = (n1 > 1) + (n2 > 1);
+  }
+  *seconds = c.ntt_limbs * r.ntt_limb_s * nscale + bconv_products * r.bconv_product_s +
+             words * N * 8 / r.hbm_bytes_per_s + layers * r.layer_s;
+  return CKKS_OK;
+}
+
+int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int max_keys, const ckks_lt_rates* rates,
+                     int* n1, int* n2, int* n3, double* predicted_s) {
+  if (!n1 || !n2 || !n3 || n_diag < 1 || log_n < 1 || log_n > 20) return CKKS_E_INVALID_ARG;
   double best = -1;
   int b1 = 0, b2 = 0, b3 = 0;
   const int nmax = 2 * n_diag;
@@ -125,22 +184,8 @@ int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int 
         ckks_lt_cost cost;
         if (ckks_lt_cost_model(log_n, level, alpha, algo, a, b, c, 64, &cost) != CKKS_OK) continue;
         if (max_keys > 0 && cost.keys > max_keys) continue;
-        // Key-switch bytes: digits, key, add-in and two outputs per product;
-        // MAC bytes: the present plaintexts, the n1 n2 (a_m, b_m) and the outputs.
-        const int limbs = algo == CKKS_LT_BSGS ? Lq : K;
-        const double N = (double)(1 << log_n);
-        const double ks_bytes = cost.keyswitch * (3.0 * beta + 3) * K * N * 8;
-        const double inner = algo == CKKS_LT_TH_BSGS ? (double)a * b : (double)a;
-        const double outer = algo == CKKS_LT_TH_BSGS ? (double)c : (double)b;
-        const double mac_bytes = ((double)n_diag + 2 * inner + 2 * outer) * limbs * N * 8;
-        double conv = 0;
-        for (int g = 0; g < beta; ++g) {
-          const int gs = std::min(alpha, Lq - alpha * g);
-          conv += (double)gs * (K - gs);
-        }
-        const double bconv_products = (cost.decompose * conv + cost.moddown * alpha * Lq) * N;
-        const double t = cost.ntt_limbs * r.ntt_limb_s * nscale + bconv_products * r.bconv_product_s +
-                         (ks_bytes + mac_bytes) / r.hbm_bytes_per_s;
+        double t;
+        if (ckks_lt_predict(log_n, level, alpha, algo, a, b, c, n_diag, rates, &t) != CKKS_OK) continue;
         if (best < 0 || t < best - 1e-12) {
           best = t;
           b1 = a;

@@ -76,3 +76,25 @@ def test_autotune_properties(n):
 def test_autotune_infeasible_budget():
     with pytest.raises(H.CkksError):
         H.ckks_lt_autotune(16, 24, 9, H.CKKS_LT_TH_BSGS, 128, 9)
+
+
+@pytest.mark.parametrize("level,n", [(24, 64), (16, 128), (8, 16)])
+def test_autotune_is_the_argmin_of_the_predictor(level, n):
+    split, t = H.ckks_lt_autotune(16, level, 9, H.CKKS_LT_TH_BSGS, n)
+    assert abs(H.ckks_lt_predict(16, level, 9, H.CKKS_LT_TH_BSGS, split, n) - t) < 1e-15
+    best = min(H.ckks_lt_predict(16, level, 9, H.CKKS_LT_TH_BSGS, (a, b, c), n)
+               for a in range(1, n + 1) for b in range(1, 2 * n // a + 1) for c in range(1, 2 * n // (a * b) + 1)
+               if n <= a * b * c < 2 * n)
+    assert t <= best + 1e-15
+
+
+def test_predictor_structure():
+    # DH-BSGS (n1, n2) is priced exactly as Algorithm 2 with (1, n1, n2)
+    assert H.ckks_lt_predict(16, 24, 9, H.CKKS_LT_DH_BSGS, (16, 4), 64) == \
+        H.ckks_lt_predict(16, 24, 9, H.CKKS_LT_TH_BSGS, (1, 16, 4), 64)
+    # more present diagonals (plaintext bytes) never predict less time
+    ts = [H.ckks_lt_predict(16, 24, 9, H.CKKS_LT_TH_BSGS, (4, 4, 4), n) for n in (1, 16, 48, 64)]
+    assert ts == sorted(ts) and ts[0] < ts[-1]
+    # lower levels are cheaper; custom rates are honoured (zero rates: zero time)
+    assert H.ckks_lt_predict(16, 8, 9, H.CKKS_LT_TH_BSGS, (4, 4, 4), 64) < ts[-1]
+    assert H.ckks_lt_predict(16, 24, 9, H.CKKS_LT_BSGS, (8, 8), 64, rates=(0.0, 0.0, 1e300, 0.0)) < 1e-200
