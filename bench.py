@@ -351,7 +351,7 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
     (resident state included)."""
     import numpy as np
     import workload as W
-    split = (8, 8, 4)
+    split = (4, 16, 4)
     rings, resident = [], 0
     for log_n in (14, 15, 16):
         prm = W.params_n16(log_n=log_n)
@@ -409,7 +409,7 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
            "arena_bytes": arena, "arena_peak_bytes": st["arena_peak"], "resident_bytes": resident,
            "burst": {"requests": min(nreq, 400), "lt_per_s": round(stb["completed"] / max(stb["span_s"], 1e-9), 1),
                      "p50_ms": round(stb["p50_s"] * 1e3, 2), "p99_ms": round(stb["p99_s"] * 1e3, 2)},
-           "recipe": "Poisson %.0f req/s, N ~ U{2^14,2^15,2^16}, level ~ U{8..24}, n ~ U{32..256}, split (8,8,4), "
+           "recipe": "Poisson %.0f req/s, N ~ U{2^14,2^15,2^16}, level ~ U{8..24}, n ~ U{32..256}, split (4,16,4), "
                      "seed %d; max_batch 8, 2 streams" % (rate, seed)}
     del rings, reqs
     torch.cuda.empty_cache()
