@@ -37,6 +37,21 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int j = 0; j < NS; ++j)
     y[j] = shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], primes[plan->src[j]].q);
+  if (plan->split30) {
+    // all primes below 2^60: the inner product from 30-bit column sums
+    uint32_t y0[NS], y1[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      y0[j] = (uint32_t)(y[j] & ((1ull << 30) - 1));
+      y1[j] = (uint32_t)(y[j] >> 30);
+    }
+    for (int m = m0; m < m1; ++m) {
+      const int di = plan->dst[m];
+      dst[(size_t)(di - shift) * n + p] = redc(dot_split30<NS>(y0, y1, plan->hmod[m]), primes[di].q,
+                                               primes[di].qinv_neg);
+    }
+    return;
+  }
   for (int m = m0; m < m1; ++m) {
     const int di = plan->dst[m];
     const uint64_t q = primes[di].q, qn = primes[di].qinv_neg;

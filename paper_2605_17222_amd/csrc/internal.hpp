@@ -64,6 +64,8 @@ struct BConvPlan {
   uint64_t hmod[kMaxDst][kMaxSrc];  // [S/s_j]_{d_m} * 2^64 mod d_m
   uint64_t sinv[kMaxDst];           // S^-1 mod d_m
   uint64_t sinv_sh[kMaxDst];
+  int split30;                      // every source and destination prime < 2^60: the
+                                    // inner product may use 30-bit column sums
 };
 
 // A run of `count` limbs stored back to back whose primes are consecutive PQ

@@ -111,6 +111,30 @@ __host__ __device__ __forceinline__ uint64_t fp_canon(double x, double q, double
   return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
+// sum_j y_j c_j for NS <= 16 terms with y_j, c_j < 2^60, from 30-bit halves
+// (y_j = y1_j 2^30 + y0_j, c_j = c1 2^30 + c0): every partial product is below
+// 2^60, so each of the four column sums stays below 2^64 and a term costs four
+// 32x32+64 multiply-adds with no carry handling; the columns are combined
+// once: c00 + (c01 + c10) 2^30 + c11 2^60 < 2^125.
+template <int NS>
+__host__ __device__ __forceinline__ U128 dot_split30(const uint32_t* y0, const uint32_t* y1, const uint64_t* c) {
+  constexpr uint64_t M30 = (1ull << 30) - 1;
+  uint64_t c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const uint32_t k0 = (uint32_t)(c[j] & M30), k1 = (uint32_t)(c[j] >> 30);
+    c00 += (uint64_t)y0[j] * k0;
+    c01 += (uint64_t)y0[j] * k1;
+    c10 += (uint64_t)y1[j] * k0;
+    c11 += (uint64_t)y1[j] * k1;
+  }
+  U128 acc = {c00, 0};
+  add128(acc, U128{c01 << 30, c01 >> 34});
+  add128(acc, U128{c10 << 30, c10 >> 34});
+  add128(acc, U128{c11 << 60, c11 >> 4});
+  return acc;
+}
+
 // Bit reversal of the low `bits` bits.
 __device__ __forceinline__ uint32_t bitrev(uint32_t x, int bits) { return __brev(x) >> (32 - bits); }
 

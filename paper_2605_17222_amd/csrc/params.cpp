@@ -80,6 +80,11 @@ int make_plan(const std::vector<uint64_t>& pr, const std::vector<int>& src, cons
   }
   // REDC of sum_j y_j c_jm needs sum_j s_j <= 2^64.
   if (sum > ((u128)1 << 64)) return CKKS_E_UNSUPPORTED;
+  pl->split30 = 1;
+  for (int j : src)
+    if (pr[j] >= (1ull << 60)) pl->split30 = 0;
+  for (int m : dst)
+    if (pr[m] >= (1ull << 60)) pl->split30 = 0;
   for (int j = 0; j < pl->ns; ++j) {
     const uint64_t sj = pr[src[j]];
     uint64_t h = 1;

@@ -75,6 +75,23 @@ int main() {
       checks += 4;
     }
   }
+  // 30-bit column sums of a basis-conversion inner product: y_j, c_j < 2^60
+  for (int it = 0; it < 200000; ++it) {
+    uint32_t y0[16], y1[16];
+    uint64_t c[16];
+    u128 ref = 0;
+    for (int j = 0; j < 16; ++j) {
+      uint64_t y = rnd() >> 4, cj = rnd() >> 4;
+      if (it < 2) y = cj = (1ull << 60) - 1;  // largest operands
+      y0[j] = (uint32_t)(y & ((1ull << 30) - 1));
+      y1[j] = (uint32_t)(y >> 30);
+      c[j] = cj;
+      if (j < 9 || it % 2) ref += (u128)y * cj;
+    }
+    const U128 d = (it % 2) ? dot_split30<16>(y0, y1, c) : dot_split30<9>(y0, y1, c);
+    fails += d.lo != (uint64_t)ref || d.hi != (uint64_t)(ref >> 64);
+    checks += 1;
+  }
   printf("%ld checks, %ld failures\n", checks, fails);
   return fails ? 1 : 0;
 }
