@@ -30,8 +30,29 @@ __global__ void __launch_bounds__(kThreads)
   const int shift = a.dst_shift[item];
   const size_t n = (size_t)1 << log_n;
   const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  // m1 <= m0 when this item has fewer destination limbs than the launch's
+  // widest item: then the chunk is empty (cnt = 0) and only the shared
+  // staging below runs (with nothing to stage).
   const int m0 = blockIdx.z * kChunk;
-  const int m1 = min(plan->nd, m0 + kChunk);
+  const int m1 = max(m0, min(plan->nd, m0 + kChunk));
+  const int cnt = m1 - m0;  // 0 .. kChunk
+
+  // The chunk's constants and primes, staged once per workgroup: read from
+  // global memory inside the destination loop they would make every
+  // iteration wait for a load.
+  __shared__ uint64_t cst[kChunk][NS];
+  __shared__ uint64_t qd[kChunk][2];
+  const int tid = (int)threadIdx.x;
+  if (tid < cnt * NS) {
+    const int mm = tid / NS, j = tid % NS;
+    cst[mm][j] = plan->hmod[m0 + mm][j];
+  }
+  if (tid < cnt) {
+    const PrimeDev& pd = primes[plan->dst[m0 + tid]];
+    qd[tid][0] = pd.q;
+    qd[tid][1] = pd.qinv_neg;
+  }
+  __syncthreads();
 
   uint64_t y[NS];
 #pragma unroll
@@ -47,15 +68,14 @@ __global__ void __launch_bounds__(kThreads)
     }
     for (int m = m0; m < m1; ++m) {
       const int di = plan->dst[m];
-      dst[(size_t)(di - shift) * n + p] = redc(dot_split30<NS>(y0, y1, plan->hmod[m]), primes[di].q,
-                                               primes[di].qinv_neg);
+      dst[(size_t)(di - shift) * n + p] = redc(dot_split30<NS>(y0, y1, cst[m - m0]), qd[m - m0][0], qd[m - m0][1]);
     }
     return;
   }
   for (int m = m0; m < m1; ++m) {
     const int di = plan->dst[m];
-    const uint64_t q = primes[di].q, qn = primes[di].qinv_neg;
-    const uint64_t* __restrict__ c = plan->hmod[m];
+    const uint64_t q = qd[m - m0][0], qn = qd[m - m0][1];
+    const uint64_t* c = cst[m - m0];
     U128 acc = mul_wide(y[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NS; ++j) add128(acc, mul_wide(y[j], c[j]));
