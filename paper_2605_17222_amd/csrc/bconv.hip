@@ -41,11 +41,14 @@ __global__ void __launch_bounds__(kThreads)
   // global memory inside the destination loop they would make every
   // iteration wait for a load.
   __shared__ uint64_t cst[kChunk][NS];
+  __shared__ uint32_t cst2[kChunk][NS][2];
   __shared__ uint64_t qd[kChunk][2];
   const int tid = (int)threadIdx.x;
   if (tid < cnt * NS) {
     const int mm = tid / NS, j = tid % NS;
     cst[mm][j] = plan->hmod[m0 + mm][j];
+    cst2[mm][j][0] = plan->hk[m0 + mm][j][0];
+    cst2[mm][j][1] = plan->hk[m0 + mm][j][1];
   }
   if (tid < cnt) {
     const PrimeDev& pd = primes[plan->dst[m0 + tid]];
@@ -68,7 +71,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     for (int m = m0; m < m1; ++m) {
       const int di = plan->dst[m];
-      dst[(size_t)(di - shift) * n + p] = redc(dot_split30<NS>(y0, y1, cst[m - m0]), qd[m - m0][0], qd[m - m0][1]);
+      dst[(size_t)(di - shift) * n + p] = redc(dot_split30<NS>(y0, y1, cst2[m - m0]), qd[m - m0][0], qd[m - m0][1]);
     }
     return;
   }

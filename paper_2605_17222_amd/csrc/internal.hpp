@@ -66,6 +66,7 @@ struct BConvPlan {
   uint64_t sinv_sh[kMaxDst];
   int split30;                      // every source and destination prime < 2^60: the
                                     // inner product may use 30-bit column sums
+  uint32_t hk[kMaxDst][kMaxSrc][2];  // hmod split into its 30-bit halves (split30)
 };
 
 // A run of `count` limbs stored back to back whose primes are consecutive PQ

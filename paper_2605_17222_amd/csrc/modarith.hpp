@@ -112,17 +112,17 @@ __host__ __device__ __forceinline__ uint64_t fp_canon(double x, double q, double
 }
 
 // sum_j y_j c_j for NS <= 16 terms with y_j, c_j < 2^60, from 30-bit halves
-// (y_j = y1_j 2^30 + y0_j, c_j = c1 2^30 + c0): every partial product is below
+// (y_j = y1_j 2^30 + y0_j, c_j = c1_j 2^30 + c0_j): every partial product is below
 // 2^60, so each of the four column sums stays below 2^64 and a term costs four
 // 32x32+64 multiply-adds with no carry handling; the columns are combined
 // once: c00 + (c01 + c10) 2^30 + c11 2^60 < 2^125.
+// k[j] = {c0, c1}: the constant already split.
 template <int NS>
-__host__ __device__ __forceinline__ U128 dot_split30(const uint32_t* y0, const uint32_t* y1, const uint64_t* c) {
-  constexpr uint64_t M30 = (1ull << 30) - 1;
+__host__ __device__ __forceinline__ U128 dot_split30(const uint32_t* y0, const uint32_t* y1, const uint32_t (*k)[2]) {
   uint64_t c00 = 0, c01 = 0, c10 = 0, c11 = 0;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    const uint32_t k0 = (uint32_t)(c[j] & M30), k1 = (uint32_t)(c[j] >> 30);
+    const uint32_t k0 = k[j][0], k1 = k[j][1];
     c00 += (uint64_t)y0[j] * k0;
     c01 += (uint64_t)y0[j] * k1;
     c10 += (uint64_t)y1[j] * k0;

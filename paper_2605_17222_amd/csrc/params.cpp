@@ -103,6 +103,8 @@ int make_plan(const std::vector<uint64_t>& pr, const std::vector<int>& src, cons
       for (int i = 0; i < pl->ns; ++i)
         if (i != j) h = mm(h, pr[src[i]] % d, d);
       pl->hmod[m][j] = mm(h, r64, d);
+      pl->hk[m][j][0] = (uint32_t)(pl->hmod[m][j] & ((1ull << 30) - 1));
+      pl->hk[m][j][1] = (uint32_t)(pl->hmod[m][j] >> 30);
       all = mm(all, pr[src[j]] % d, d);
     }
     pl->sinv[m] = inv(all, d);

@@ -77,7 +77,7 @@ int main() {
   }
   // 30-bit column sums of a basis-conversion inner product: y_j, c_j < 2^60
   for (int it = 0; it < 200000; ++it) {
-    uint32_t y0[16], y1[16];
+    uint32_t y0[16], y1[16], c2[16][2];
     uint64_t c[16];
     u128 ref = 0;
     for (int j = 0; j < 16; ++j) {
@@ -86,9 +86,11 @@ int main() {
       y0[j] = (uint32_t)(y & ((1ull << 30) - 1));
       y1[j] = (uint32_t)(y >> 30);
       c[j] = cj;
+      c2[j][0] = (uint32_t)(cj & ((1ull << 30) - 1));
+      c2[j][1] = (uint32_t)(cj >> 30);
       if (j < 9 || it % 2) ref += (u128)y * cj;
     }
-    const U128 d = (it % 2) ? dot_split30<16>(y0, y1, c) : dot_split30<9>(y0, y1, c);
+    const U128 d = (it % 2) ? dot_split30<16>(y0, y1, c2) : dot_split30<9>(y0, y1, c2);
     fails += d.lo != (uint64_t)ref || d.hi != (uint64_t)(ref >> 64);
     checks += 1;
   }
