@@ -18,7 +18,7 @@ namespace ckks {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 6;  // destination limbs per workgroup (grid.z splits the rest)
+constexpr int kChunk = 27;  // destination limbs per workgroup (grid.z splits the rest)
 
 template <int NS>
 __global__ void __launch_bounds__(kThreads)
@@ -44,16 +44,16 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ uint32_t cst2[kChunk][NS][2];
   __shared__ uint64_t qd[kChunk][2];
   const int tid = (int)threadIdx.x;
-  if (tid < cnt * NS) {
-    const int mm = tid / NS, j = tid % NS;
+  for (int e = tid; e < cnt * NS; e += kThreads) {
+    const int mm = e / NS, j = e % NS;
     cst[mm][j] = plan->hmod[m0 + mm][j];
     cst2[mm][j][0] = plan->hk[m0 + mm][j][0];
     cst2[mm][j][1] = plan->hk[m0 + mm][j][1];
   }
-  if (tid < cnt) {
-    const PrimeDev& pd = primes[plan->dst[m0 + tid]];
-    qd[tid][0] = pd.q;
-    qd[tid][1] = pd.qinv_neg;
+  for (int e = tid; e < cnt; e += kThreads) {
+    const PrimeDev& pd = primes[plan->dst[m0 + e]];
+    qd[e][0] = pd.q;
+    qd[e][1] = pd.qinv_neg;
   }
   __syncthreads();
 

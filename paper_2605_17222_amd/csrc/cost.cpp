@@ -111,7 +111,7 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
     // Fitted on one MI355X at N = 2^16 (levels 8..24, 16..511 diagonals,
     // 120 splits; mean prediction error 7%): BConv from its own kernel time.
     r.ntt_limb_s = 4.19e-7;
-    r.bconv_product_s = 0.77e-12;
+    r.bconv_product_s = 0.59e-12;
     r.hbm_bytes_per_s = 4.06e12;
     r.layer_s = 45e-6;
   }
