@@ -27,15 +27,37 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
+def _jobs() -> int:
+    try:
+        n = int(os.environ.get("MAX_JOBS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(n or (os.cpu_count() or 1), 16))
+
+
 def build(verbose: bool = False) -> str:
+    """Compiles every source to an object in parallel, then links the library."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + FLAGS + sources() + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building %s" % LIB)
+    with tempfile.TemporaryDirectory(prefix="ckks_build_") as od:
+        srcs = sources()
+        objs = [os.path.join(od, os.path.basename(f) + ".o") for f in srcs]
+        compile_flags = [f for f in FLAGS if f != "-shared"]
+
+        def run(cmd):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            return subprocess.run(cmd, capture_output=True, text=True)
+
+        with ThreadPoolExecutor(_jobs()) as ex:
+            rs = list(ex.map(run, [["hipcc"] + compile_flags + ["-c", f, "-o", o] for f, o in zip(srcs, objs)]))
+        rs.append(run(["hipcc"] + FLAGS + objs + ["-o", tmp]) if all(r.returncode == 0 for r in rs) else rs[0])
+        for r in rs:
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError("hipcc failed building %s" % LIB)
     os.replace(tmp, LIB)
     return LIB
 
