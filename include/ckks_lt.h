@@ -112,6 +112,17 @@ typedef struct {
  * A NULL pointer is an all-zero diagonal and is skipped exactly.  The
  * progression must not repeat an offset: n1 n2 n3 (or n_diag) indices at
  * most N/2 / gcd(s, N/2).
+ *
+ * On-the-fly plaintexts (TH-BSGS and DH-BSGS only): with pt = NULL and
+ * slots set, slots[t] is the diagonal itself as N/2 complex slot values
+ * (device [N/2][2] doubles, re and im; NULL = absent) and the library encodes
+ * f^_t = encode(rot(diag_t, -G_k)) with scale pt_scale at the ciphertext's
+ * level (as ckks_encode does) right before the multiply-accumulate that
+ * consumes it, so no plaintext outlives its use: a dense n = N/2 matrix
+ * needs N/2 slot vectors (16 B per slot) instead of n resident plaintexts of
+ * alpha + l + 1 limbs.  The workspace then also holds the plaintexts of one
+ * multiply-accumulate launch (up to 128 of alpha + l + 1 limbs).  Setting
+ * both pt and slots is an error.
  */
 typedef struct {
   int n1, n2, n3;                /* split; n3 = 1 for BSGS; ignored by naive */
@@ -120,6 +131,7 @@ typedef struct {
   double pt_scale;               /* scale the plaintexts were encoded with   */
   int stride;                    /* s; 0 reads as 1                          */
   int centre;                    /* c                                        */
+  const double* const* slots;    /* host [n_diag] of device pointers or NULL */
 } ckks_lt_diags;
 
 /*
@@ -163,6 +175,41 @@ int ckks_lt_workspace_size(const ckks_params* params, int level, const ckks_lt_d
  */
 int ckks_lt_eval(const ckks_params* params, const ckks_ct* in, const ckks_lt_diags* diags,
                  const ckks_rotkeys* keys, int algo, ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- plaintext encoding on the device ------------------------------------- */
+/*
+ * Encoding (Section II-A): the plaintext of a vector z of N/2 complex slots
+ * is the integer polynomial m = round(scale * sigma^-1(z)), where slot t is
+ * m(zeta^(5^t)), zeta = e^(i pi / N); rounding is half away from zero.  The
+ * library computes it with one length-N/2 complex FFT in FP64 per vector,
+ * reduces m into the primes first_prime .. first_prime + n_limbs - 1 of the
+ * PQ chain (P first: TH-BSGS plaintexts at level l are primes 0 .. alpha + l,
+ * BSGS plaintexts primes alpha .. alpha + l) and returns NTT form.  Item i
+ * encodes rot(z, rot): slot t takes z[(t + rot) mod N/2], so the giant-step
+ * pre-rotation phi_{-G}(f) of Algorithm 2 is rot = -G.
+ *   slots: device [N/2][2] doubles (re, im), read only
+ *   out:   device [n_limbs][N] words, written
+ *   coef:  device [N] int64 or NULL: receives m
+ * |scale * sigma^-1(z)| must stay below 2^62 (coefficients beyond are
+ * clamped).  FP64 rounding decides m: a coefficient within a few ulp of a
+ * half-integer may round either way relative to another FFT.
+ * Errors: CKKS_E_INVALID_ARG (nulls, scale not positive and finite, prime
+ * range outside the chain), CKKS_E_WORKSPACE, CKKS_E_DEVICE.  Enqueues on
+ * stream and returns.
+ */
+typedef struct {
+  const double* slots;
+  int32_t rot;
+  uint64_t* out;
+  int64_t* coef;
+} ckks_encode_item;
+
+/* Workspace bytes ckks_encode needs for count items (at most two limbs per
+ * item, for at most 32 items). */
+int ckks_encode_workspace_size(const ckks_params* params, int count, size_t* bytes);
+
+int ckks_encode(const ckks_params* params, int count, const ckks_encode_item* items, double scale, int first_prime,
+                int n_limbs, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- ragged batches --------------------------------------------------------- */
 /*
@@ -238,7 +285,7 @@ typedef struct ckks_server ckks_server;  /* opaque */
 typedef struct {
   int ring;               /* id from ckks_server_add_ring                      */
   ckks_ct in;             /* device; complete before submission                */
-  ckks_lt_diags diags;    /* TH-BSGS split; pt array is copied at submission   */
+  ckks_lt_diags diags;    /* TH-BSGS split; pt (or slots) array copied at submission */
   ckks_ct out;            /* device; written when the request completes        */
   size_t sim_ws_bytes;    /* simulated backend only: the request's workspace   */
 } ckks_request;
@@ -421,7 +468,9 @@ int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int 
 #define CKKS_KERNEL_PTMAC 6
 #define CKKS_KERNEL_AUTOMORPH 7
 #define CKKS_KERNEL_KEYSWITCH_GATHER 8
-#define CKKS_KERNEL_COUNT 9
+#define CKKS_KERNEL_ENCODE_FFT 9  /* plaintext encoding: the two FFT passes  */
+#define CKKS_KERNEL_ENCODE_RNS 10 /* plaintext encoding: residues of m      */
+#define CKKS_KERNEL_COUNT 11
 
 /*
  * Process-wide: for every kernel k with bit (1 << k) set in mask, each later

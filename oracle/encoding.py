@@ -30,6 +30,11 @@ def _round_away(x: np.ndarray) -> np.ndarray:
 
 def encode(z: np.ndarray, scale: float, n: int) -> np.ndarray:
     """Integer coefficients (int64) of round(scale * sigma^-1(z))."""
+    return _round_away(encode_unrounded(z, scale, n)).astype(np.int64)
+
+
+def encode_unrounded(z: np.ndarray, scale: float, n: int) -> np.ndarray:
+    """scale * sigma^-1(z) as float64, before the rounding of encode()."""
     s = n // 2
     z = np.asarray(z, dtype=np.complex128)
     assert z.shape == (s,)
@@ -41,7 +46,7 @@ def encode(z: np.ndarray, scale: float, n: int) -> np.ndarray:
     zeta_neg = np.exp(-1j * np.pi * k / n)
     # m_k = (1/N) sum_l w_l zeta^-(2l+1)k = zeta^-k/N * sum_l w_l e^{-2 pi i lk/N}
     m = (np.fft.fft(w) * zeta_neg / n).real
-    return _round_away(m * scale).astype(np.int64)
+    return m * scale
 
 
 def decode(m: np.ndarray, scale: float, n: int) -> np.ndarray:

@@ -43,10 +43,11 @@ EXPORTED = [
     "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch", "ckks_lt_cost_model", "ckks_lt_autotune",
     "ckks_lt_predict", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit", "ckks_server_poll",
     "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats", "ckks_server_destroy",
+    "ckks_encode_workspace_size", "ckks_encode",
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
-           "automorph", "keyswitch_gather"]
+           "automorph", "keyswitch_gather", "encode_fft", "encode_rns"]
 
 
 class CkksError(RuntimeError):
@@ -71,7 +72,12 @@ class Ct(ctypes.Structure):
 class Diags(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("n_diag", ctypes.c_int),
                 ("pt", ctypes.POINTER(ctypes.c_void_p)), ("pt_scale", ctypes.c_double), ("stride", ctypes.c_int),
-                ("centre", ctypes.c_int)]
+                ("centre", ctypes.c_int), ("slots", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class EncodeItem(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_void_p), ("rot", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p)]
 
 
 class RotKeys(ctypes.Structure):
@@ -181,6 +187,9 @@ def lib() -> ctypes.CDLL:
         L.ckks_server_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServerStat)]
         L.ckks_server_destroy.argtypes = [ctypes.c_void_p]
         L.ckks_server_destroy.restype = None
+        L.ckks_encode_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.ckks_encode.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(EncodeItem), ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -258,11 +267,14 @@ def ckks_params_info(params: Params) -> Tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
-def _diags(split: Sequence[int], pts: Sequence, pt_scale: float, stride: int = 1, centre: int = 0):
+def _diags(split: Sequence[int], pts: Sequence, pt_scale: float, stride: int = 1, centre: int = 0,
+           onfly: bool = False):
+    """onfly: pts holds slot vectors (complex128 device tensors of N/2
+    entries, or None) that the library encodes itself."""
     n1, n2, n3 = (list(split) + [1, 1])[:3]
     arr = (ctypes.c_void_p * max(1, len(pts)))(*[_ptr(x) for x in pts])
-    return Diags(n1, n2, n3, len(pts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), pt_scale, stride,
-                 centre), arr
+    p = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    return Diags(n1, n2, n3, len(pts), None if onfly else p, pt_scale, stride, centre, p if onfly else None), arr
 
 
 def _keys(keys: Optional[Dict[int, object]]):
@@ -275,8 +287,8 @@ def _keys(keys: Optional[Dict[int, object]]):
 
 
 def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts: Sequence, algo: int,
-                           stride: int = 1, centre: int = 0) -> int:
-    d, keep = _diags(split, pts, 1.0, stride, centre)
+                           stride: int = 1, centre: int = 0, onfly: bool = False) -> int:
+    d, keep = _diags(split, pts, 1.0, stride, centre, onfly)
     out = ctypes.c_size_t()
     _check(lib().ckks_lt_workspace_size(params, level, ctypes.byref(d), algo, ctypes.byref(out)),
            "ckks_lt_workspace_size")
@@ -285,11 +297,12 @@ def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts
 
 def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequence[int], pts: Sequence,
                  pt_scale: float, keys: Optional[Dict[int, object]], algo: int, out0, out1, ws, ws_bytes: int,
-                 stream=None, stride: int = 1, centre: int = 0) -> Tuple[int, float]:
-    """Enqueue out = LT(in); returns (out level, out scale)."""
+                 stream=None, stride: int = 1, centre: int = 0, onfly: bool = False) -> Tuple[int, float]:
+    """Enqueue out = LT(in); returns (out level, out scale).  onfly: pts are
+    slot vectors encoded by the library with pt_scale (TH-/DH-BSGS)."""
     cin = Ct(level, scale, _ptr(c0), _ptr(c1))
     cout = Ct(level - 1, 0.0, _ptr(out0), _ptr(out1))
-    d, keep1 = _diags(split, pts, pt_scale, stride, centre)
+    d, keep1 = _diags(split, pts, pt_scale, stride, centre, onfly)
     k, keep2 = _keys(keys)
     _check(lib().ckks_lt_eval(params, ctypes.byref(cin), ctypes.byref(d), ctypes.byref(k), algo,
                               ctypes.byref(cout), _ptr(ws), ws_bytes, _stream(stream)), "ckks_lt_eval")
@@ -299,9 +312,10 @@ def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequen
 class BatchItem:
     """One LT of a batch (device buffers as tensors or int addresses)."""
 
-    def __init__(self, level, scale, c0, c1, split, pts, pt_scale, keys, out0, out1, stride=1, centre=0):
+    def __init__(self, level, scale, c0, c1, split, pts, pt_scale, keys, out0, out1, stride=1, centre=0,
+                 onfly=False):
         self.level, self.scale, self.c0, self.c1 = level, scale, c0, c1
-        self.stride, self.centre = stride, centre
+        self.stride, self.centre, self.onfly = stride, centre, onfly
         self.split, self.pts, self.pt_scale, self.keys = split, pts, pt_scale, keys
         self.out0, self.out1 = out0, out1
         self.status = None
@@ -312,7 +326,7 @@ def _items(items: Sequence[BatchItem]):
     arr = (LtItem * max(1, len(items)))()
     keep = []
     for t, it in enumerate(items):
-        d, k1 = _diags(it.split, it.pts, it.pt_scale, it.stride, it.centre)
+        d, k1 = _diags(it.split, it.pts, it.pt_scale, it.stride, it.centre, it.onfly)
         ks, k2 = _keys(it.keys)
         keep += [d, k1, ks, k2]
         arr[t].in_ = Ct(it.level, it.scale, _ptr(it.c0), _ptr(it.c1))
@@ -387,9 +401,10 @@ def ckks_server_add_ring(server: Server, params: Optional[Params], keys: Optiona
 
 def ckks_server_submit(server: Server, ring: int, level: int = 0, scale: float = 0.0, c0=None, c1=None,
                        split: Sequence[int] = (1, 1, 1), pts: Sequence = (), pt_scale: float = 0.0, out0=None,
-                       out1=None, sim_ws_bytes: int = 0, stride: int = 1, centre: int = 0) -> int:
+                       out1=None, sim_ws_bytes: int = 0, stride: int = 1, centre: int = 0,
+                       onfly: bool = False) -> int:
     """Queue one TH-BSGS LT; returns the request id (raises if refused)."""
-    d, keep = _diags(split, pts, pt_scale, stride, centre)
+    d, keep = _diags(split, pts, pt_scale, stride, centre, onfly)
     rq = Request(ring, Ct(level, scale, _ptr(c0), _ptr(c1)), d, Ct(level - 1, 0.0, _ptr(out0), _ptr(out1)),
                  sim_ws_bytes)
     rid = ctypes.c_uint64()
@@ -452,6 +467,25 @@ def ckks_lt_autotune(log_n: int, level: int, alpha: int, algo: int, n_diag: int,
     _check(lib().ckks_lt_autotune(log_n, level, alpha, algo, n_diag, max_keys, r, ctypes.byref(a), ctypes.byref(b),
                                   ctypes.byref(c), ctypes.byref(t)), "ckks_lt_autotune")
     return (a.value, b.value, c.value), t.value
+
+
+def ckks_encode_workspace_size(params: Params, count: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().ckks_encode_workspace_size(params, count, ctypes.byref(out)), "ckks_encode_workspace_size")
+    return out.value
+
+
+def ckks_encode(params: Params, slots: Sequence, rots: Sequence[int], scale: float, first_prime: int, n_limbs: int,
+                outs: Sequence, ws, ws_bytes: int, coefs: Optional[Sequence] = None, stream=None):
+    """Enqueue the encoding of slot vectors slots[i] (complex128 device
+    tensors of N/2 entries) as rot(z, rots[i]) into outs[i] ([n_limbs][N]
+    NTT form); coefs[i] (int64 [N] or None) receives the integers."""
+    n = len(slots)
+    arr = (EncodeItem * max(1, n))()
+    for i in range(n):
+        arr[i] = EncodeItem(_ptr(slots[i]), int(rots[i]), _ptr(outs[i]), _ptr(coefs[i]) if coefs else None)
+    _check(lib().ckks_encode(params, n, arr, scale, first_prime, n_limbs, _ptr(ws), ws_bytes, _stream(stream)),
+           "ckks_encode")
 
 
 def ckks_op_ntt(params: Params, forward: bool, first_prime: int, n_limbs: int, x, out, stream=None):

@@ -167,6 +167,27 @@ class ProfScope {
   bool active_ = false;
 };
 
+// Plaintext encoding of up to kMaxEnc slot vectors per launch: z[i] holds
+// N/2 complex slots (re, im), encoded as rot(z, rot[i]) with scale[i]; y[i]
+// is scratch for N/2 complex values; coef[i] receives the N coefficients.
+constexpr int kMaxEnc = 32;
+struct EncArgs {
+  int count;
+  const double* z[kMaxEnc];
+  int rot[kMaxEnc];
+  double scale[kMaxEnc];
+  double* y[kMaxEnc];
+  int64_t* coef[kMaxEnc];
+};
+// Signed coefficients coef[i] -> residues out[i] + l N of primes prime0[i] + l.
+struct RnsArgs {
+  int count;
+  const int64_t* coef[kMaxEnc];
+  uint64_t* out[kMaxEnc];
+  int prime0[kMaxEnc];
+  int nlimbs[kMaxEnc];
+};
+
 // Kernel launchers.
 hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
                       hipStream_t s);
@@ -175,6 +196,8 @@ hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipS
 hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGatherArgs& a, hipStream_t s);
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
 hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
+hipError_t launch_encode_fft(const struct ::ckks_params* P, const EncArgs& a, hipStream_t s);
+hipError_t launch_encode_rns(const struct ::ckks_params* P, const RnsArgs& a, hipStream_t s);
 
 }  // namespace ckks
 
@@ -187,6 +210,11 @@ struct ckks_params {
   uint64_t* d_tw = nullptr;            // device [K_max][4][N]
   double* d_trow = nullptr;            // device [K_max][2][ntt_row_tables_size]
   ckks::BConvPlan* d_plans = nullptr;  // device plan table
+  // Encoding tables (N/2 entries each): perm[j] = t with 5^t = 4 j + 1 mod 2N;
+  // enc_tw[e] = e^(-2 pi i e / (N/2)); enc_zinv[k] = zeta^-k / (N/2), as (re, im).
+  int* d_enc_perm = nullptr;
+  double* d_enc_tw = nullptr;
+  double* d_enc_zinv = nullptr;
   std::vector<int> plan_decomp;        // level * beta_max + b -> plan index
   std::vector<int> plan_moddown, plan_mdrescale, plan_rescale;  // per level
   int beta_max = 0;

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <vector>
 
@@ -279,6 +280,55 @@ void keyswitch(Run& R, const std::vector<KsTask>& tasks) {
   }
 }
 
+// ---- plaintext encoding -------------------------------------------------------
+
+// One plaintext: round(scale sigma^-1(rot(z, rot))) over n_limbs primes from
+// first_prime, in NTT form at out; coef (optional) receives the integers.
+struct EncItem {
+  const double* z;
+  long rot;
+  double scale;
+  int first_prime, n_limbs;
+  uint64_t* out;
+  int64_t* coef;
+};
+
+// FFT passes, residues and forward NTTs of up to kMaxEnc items per launch.
+void encode(Run& R, const std::vector<EncItem>& items) {
+  const long S = R.P->n / 2;
+  for (size_t i0 = 0; i0 < items.size(); i0 += kMaxEnc) {
+    const size_t mark = R.ws.mark();
+    const int cnt = (int)std::min<size_t>(kMaxEnc, items.size() - i0);
+    EncArgs ea;
+    RnsArgs ra;
+    memset(&ea, 0, sizeof(ea));
+    memset(&ra, 0, sizeof(ra));
+    ea.count = ra.count = cnt;
+    for (int c = 0; c < cnt; ++c) {
+      const EncItem& it = items[i0 + c];
+      ea.z[c] = it.z;
+      ea.rot[c] = (int)(((it.rot % S) + S) % S);
+      ea.scale[c] = it.scale;
+      ea.y[c] = reinterpret_cast<double*>(R.limbs(1));  // N/2 complex values
+      ea.coef[c] = it.coef ? it.coef : reinterpret_cast<int64_t*>(R.limbs(1));
+      ra.coef[c] = ea.coef[c];
+      ra.out[c] = it.out;
+      ra.prime0[c] = it.first_prime;
+      ra.nlimbs[c] = it.n_limbs;
+    }
+    if (R.live()) {
+      R.check(launch_encode_fft(R.P, ea, R.s));
+      if (R.live()) R.check(launch_encode_rns(R.P, ra, R.s));
+      NttBatch fwd(R, true);
+      for (int c = 0; c < cnt; ++c) {
+        const EncItem& it = items[i0 + c];
+        fwd.add(range(it.out, it.out, it.first_prime, it.n_limbs));
+      }
+    }
+    R.ws.reset(mark);
+  }
+}
+
 // ---- plaintext multiply-accumulate --------------------------------------------
 
 struct MacTerm {
@@ -286,12 +336,20 @@ struct MacTerm {
   const uint64_t* b;
   bool pscaled;
   std::vector<const uint64_t*> f;  // per output k (null = absent)
+  std::vector<const double*> z;    // per output k, if encoded on the fly: the slots (null = absent)
+};
+
+// How on-the-fly plaintexts are encoded: output k's with rot(z, rot[k]).
+struct MacEnc {
+  std::vector<long> rot;
+  double scale = 0;
 };
 
 // outs[k] = sum_m terms[m] * f[k], over nlimbs limbs starting at prime_off.
+// Terms with z get their plaintexts encoded right before the launch that
+// reads them, into workspace that the next launch reuses.
 void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms, const std::vector<uint64_t*>& o0,
-           const std::vector<uint64_t*>& o1) {
-  if (!R.live()) return;
+           const std::vector<uint64_t*>& o1, const MacEnc* enc = nullptr) {
   const int nk_all = (int)o0.size();
   for (int k0 = 0; k0 < nk_all; k0 += kMaxMacK) {
     const int nk = std::min(kMaxMacK, nk_all - k0);
@@ -303,6 +361,8 @@ void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms,
       ma.K = nlimbs;
       ma.prime_off = prime_off;
       ma.accumulate = first ? 0 : 1;
+      const size_t mark = R.ws.mark();
+      std::vector<EncItem> pts;
       int nm = 0;
       for (size_t m = m0; m < std::min(terms.size(), m0 + kMaxMacM); ++m, ++nm) {
         ma.a[nm] = terms[m].a;
@@ -310,18 +370,28 @@ void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms,
         if (terms[m].pscaled) {
           if (nm != 0) {
             R.fail(CKKS_E_INVALID_ARG);
+            R.ws.reset(mark);
             return;
           }
           ma.pscaled0 = 1;
         }
-        for (int k = 0; k < nk; ++k) ma.f[k][nm] = terms[m].f[k0 + k];
+        for (int k = 0; k < nk; ++k) {
+          ma.f[k][nm] = terms[m].f[k0 + k];
+          if (enc && !terms[m].z.empty() && terms[m].z[k0 + k]) {
+            uint64_t* buf = R.limbs(nlimbs);
+            pts.push_back(EncItem{terms[m].z[k0 + k], enc->rot[k0 + k], enc->scale, prime_off, nlimbs, buf, nullptr});
+            ma.f[k][nm] = buf;
+          }
+        }
       }
       ma.nm = nm;
       for (int k = 0; k < nk; ++k) {
         ma.out0[k] = o0[k0 + k];
         ma.out1[k] = o1[k0 + k];
       }
-      R.check(launch_ptmac(R.P, ma, R.s));
+      encode(R, pts);
+      if (R.live()) R.check(launch_ptmac(R.P, ma, R.s));
+      R.ws.reset(mark);
       first = false;
     }
   }
@@ -399,10 +469,14 @@ void rotate(Run& R, int level, const std::vector<RotJob>& jobs, const KeySet& ks
   }
 }
 
+// The diagonals: encoded plaintexts pt, or slot vectors z encoded on the fly
+// with scale zscale.
 struct Diag {
   int n = 0;
   const uint64_t* const* pt = nullptr;
-  bool has(int m) const { return m >= 0 && m < n && pt[m] != nullptr; }
+  const double* const* z = nullptr;
+  double zscale = 0;
+  bool has(int m) const { return m >= 0 && m < n && (z ? z[m] != nullptr : pt[m] != nullptr); }
 };
 
 // ---- triple-hoisted BSGS, Algorithm 2, for one or many ciphertexts ----------------
@@ -546,18 +620,27 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     std::vector<MacTerm> terms;
     for (int m = 0; m < inner; ++m) {
       if (!it.used_m[m]) continue;
-      MacTerm t{m == 0 ? it.c0 : it.A[m], m == 0 ? it.c1 : it.B[m], m == 0, {}};
-      for (int k : kk) t.f.push_back(k >= 0 && it.D.has(k * inner + m) ? it.D.pt[k * inner + m] : nullptr);
+      MacTerm t{m == 0 ? it.c0 : it.A[m], m == 0 ? it.c1 : it.B[m], m == 0, {}, {}};
+      for (int k : kk) {
+        const bool h = k >= 0 && it.D.has(k * inner + m);
+        if (it.D.z)
+          t.z.push_back(h ? it.D.z[k * inner + m] : nullptr);
+        t.f.push_back(h && !it.D.z ? it.D.pt[k * inner + m] : nullptr);
+      }
       terms.push_back(t);
     }
     // No diagonal at all: the result is an encryption of zero.
-    if (terms.empty()) terms.push_back(MacTerm{it.c0, it.c1, true, std::vector<const uint64_t*>(kk.size(), nullptr)});
+    if (terms.empty())
+      terms.push_back(MacTerm{it.c0, it.c1, true, std::vector<const uint64_t*>(kk.size(), nullptr), {}});
     std::vector<uint64_t*> o0, o1;
+    MacEnc enc;
+    enc.scale = it.D.zscale;
     for (int k : kk) {
       o0.push_back(k >= 0 ? it.U0[k] : it.acc0);
       o1.push_back(k >= 0 ? it.U1[k] : it.acc1);
+      enc.rot.push_back(k >= 0 ? -it.giant(P, k) : 0);  // f^ = encode(rot(diag, -G_k))
     }
-    ptmac(R, K, 0, terms, o0, o1);
+    ptmac(R, K, 0, terms, o0, o1, it.D.z ? &enc : nullptr);
   }
   // Lines 13-18: outer rotations by G_k: ModDown and Decompose of every
   // (item, k) at once, then per item one gather kernel adds
@@ -726,7 +809,12 @@ int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* dia
   if (!in || !diags || !out) return CKKS_E_INVALID_ARG;
   const int level = in->level;
   if (level < 1 || level > P->L) return CKKS_E_INVALID_ARG;
-  if (diags->n_diag < 0 || (diags->n_diag > 0 && !diags->pt)) return CKKS_E_INVALID_ARG;
+  if (diags->n_diag < 0 || (diags->n_diag > 0 && !diags->pt && !diags->slots) || (diags->pt && diags->slots))
+    return CKKS_E_INVALID_ARG;
+  if (diags->slots) {
+    if (algo != CKKS_LT_TH_BSGS && algo != CKKS_LT_DH_BSGS) return CKKS_E_UNSUPPORTED;
+    if (!(diags->pt_scale > 0) || !std::isfinite(diags->pt_scale)) return CKKS_E_INVALID_ARG;
+  }
   if (check_buffers) {
     if (!in->c0 || !in->c1 || !out->c0 || !out->c1) return CKKS_E_INVALID_ARG;
     const size_t N = (size_t)P->n;
@@ -785,6 +873,8 @@ ThItem th_item(const ckks_ct* in, const ckks_lt_diags* d, const KeySet* ks, ckks
   it.centre = d->centre;
   it.D.n = d->n_diag;
   it.D.pt = d->pt;
+  it.D.z = d->slots;
+  it.D.zscale = d->pt_scale;
   it.ks = ks;
   it.o0 = out->c0;
   it.o1 = out->c1;
@@ -923,6 +1013,49 @@ int ckks_lt_eval(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* d
     out->level = in->level - 1;
     out->scale = in->scale * diags->pt_scale / (double)P->primes[P->alpha + in->level];
     return CKKS_OK;
+  } catch (...) {
+    return CKKS_E_NOMEM;
+  }
+}
+
+static int encode_common(const ckks_params* P, int count, const ckks_encode_item* items, double scale,
+                         int first_prime, int n_limbs, void* ws, size_t ws_bytes, void* stream, bool plan_only,
+                         size_t* need) {
+  if (!P || count < 0 || (count > 0 && !items) || !(scale > 0) || !std::isfinite(scale) || first_prime < 0 ||
+      n_limbs < 1 || first_prime + n_limbs > P->Kmax())
+    return CKKS_E_INVALID_ARG;
+  std::vector<EncItem> its;
+  for (int i = 0; i < count; ++i) {
+    if (!plan_only && (!items[i].slots || !items[i].out)) return CKKS_E_INVALID_ARG;
+    its.push_back(EncItem{items[i].slots, (long)items[i].rot, scale, first_prime, n_limbs, items[i].out,
+                          plan_only ? nullptr : items[i].coef});
+  }
+  Run D = make_run(P, stream, true, nullptr);
+  encode(D, its);
+  if (need) *need = D.ws.peak;
+  if (plan_only) return CKKS_OK;
+  if (D.ws.peak > ws_bytes || (D.ws.peak > 0 && !ws)) return CKKS_E_WORKSPACE;
+  Run X = make_run(P, stream, false, ws);
+  encode(X, its);
+  return X.err;
+}
+
+int ckks_encode_workspace_size(const ckks_params* P, int count, size_t* bytes) {
+  if (!bytes) return CKKS_E_INVALID_ARG;
+  try {
+    std::vector<ckks_encode_item> items((size_t)std::max(count, 0));
+    return encode_common(P, count, items.data(), 1.0, 0, 1, nullptr, 0, nullptr, true, bytes);
+  } catch (...) {
+    return CKKS_E_NOMEM;
+  }
+}
+
+int ckks_encode(const ckks_params* P, int count, const ckks_encode_item* items, double scale, int first_prime,
+                int n_limbs, void* ws, size_t ws_bytes, void* stream) {
+  if (!P) return CKKS_E_INVALID_ARG;
+  try {
+    DeviceGuard dg(P->device);
+    return encode_common(P, count, items, scale, first_prime, n_limbs, ws, ws_bytes, stream, false, nullptr);
   } catch (...) {
     return CKKS_E_NOMEM;
   }

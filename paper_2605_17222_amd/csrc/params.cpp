@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <set>
 
 #include "host_util.hpp"
@@ -293,11 +294,35 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
     }
   }
 
+  // Encoding tables.
+  const int S = n / 2;
+  std::vector<int> perm(S, -1);
+  std::vector<double> etw(2 * (size_t)S), ezinv(2 * (size_t)S);
+  {
+    uint64_t e = 1;
+    for (int t = 0; t < S; ++t) {
+      perm[(e - 1) / 4] = t;
+      e = e * 5 % two_n;
+    }
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < S; ++k) {
+      const long double a = -2 * pi * (long double)k / (long double)S;
+      etw[2 * k] = (double)std::cos(a);
+      etw[2 * k + 1] = (double)std::sin(a);
+      const long double b = -pi * (long double)k / (long double)n;
+      ezinv[2 * k] = (double)(std::cos(b) / S);
+      ezinv[2 * k + 1] = (double)(std::sin(b) / S);
+    }
+  }
+
   // Upload.
   if (hipMalloc(&P->d_tw, tw.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_trow, trow.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_primes, pd.size() * sizeof(PrimeDev)) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_plans, plans.size() * sizeof(BConvPlan)) != hipSuccess) return CKKS_E_NOMEM;
+  if (hipMalloc(&P->d_enc_perm, perm.size() * sizeof(int)) != hipSuccess) return CKKS_E_NOMEM;
+  if (hipMalloc(&P->d_enc_tw, etw.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
+  if (hipMalloc(&P->d_enc_zinv, ezinv.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
   for (int i = 0; i < K; ++i) {
     pd[i].tw = P->d_tw + (size_t)i * 4 * n;
     pd[i].trow = P->d_trow + (size_t)i * 2 * rts;
@@ -307,6 +332,10 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
   if (hipMemcpy(P->d_primes, pd.data(), pd.size() * sizeof(PrimeDev), hipMemcpyHostToDevice) != hipSuccess)
     return CKKS_E_DEVICE;
   if (hipMemcpy(P->d_plans, plans.data(), plans.size() * sizeof(BConvPlan), hipMemcpyHostToDevice) != hipSuccess)
+    return CKKS_E_DEVICE;
+  if (hipMemcpy(P->d_enc_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->d_enc_tw, etw.data(), etw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->d_enc_zinv, ezinv.data(), ezinv.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     return CKKS_E_DEVICE;
   *out = guard.release();
   return CKKS_OK;
@@ -321,6 +350,9 @@ void params_destroy(ckks_params* P) {
   if (P->d_trow) (void)hipFree(P->d_trow);
   if (P->d_primes) (void)hipFree(P->d_primes);
   if (P->d_plans) (void)hipFree(P->d_plans);
+  if (P->d_enc_perm) (void)hipFree(P->d_enc_perm);
+  if (P->d_enc_tw) (void)hipFree(P->d_enc_tw);
+  if (P->d_enc_zinv) (void)hipFree(P->d_enc_zinv);
   if (cur >= 0 && cur != P->device) (void)hipSetDevice(cur);
   delete P;
 }

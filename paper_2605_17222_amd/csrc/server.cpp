@@ -40,6 +40,7 @@ struct Request {
   int ring = 0;
   ckks_lt_item item{};
   std::vector<const uint64_t*> pts;  // own copy of the plaintext pointer array
+  std::vector<const double*> slots;  // or of the slot-vector pointer array
   size_t ws_need = 0;                // simulated backend
   int status = CKKS_PENDING;
   double t_submit = 0, t_start = 0, t_done = 0;
@@ -346,7 +347,8 @@ int ckks_server_add_ring(ckks_server* S, const ckks_params* params, const ckks_r
 }
 
 int ckks_server_submit(ckks_server* S, const ckks_request* rq, uint64_t* id) {
-  if (!S || !rq || !id || rq->ring < 0 || rq->diags.n_diag < 0 || (rq->diags.n_diag > 0 && !rq->diags.pt))
+  if (!S || !rq || !id || rq->ring < 0 || rq->diags.n_diag < 0 ||
+      (rq->diags.n_diag > 0 && !rq->diags.pt && !rq->diags.slots) || (rq->diags.pt && rq->diags.slots))
     return CKKS_E_INVALID_ARG;
   Request* r = nullptr;
   try {
@@ -356,8 +358,13 @@ int ckks_server_submit(ckks_server* S, const ckks_request* rq, uint64_t* id) {
     r->item.diags = rq->diags;
     r->item.out = rq->out;
     r->item.status = CKKS_OK;
-    r->pts.assign(rq->diags.pt, rq->diags.pt + rq->diags.n_diag);
-    r->item.diags.pt = r->pts.data();
+    if (rq->diags.pt) {
+      r->pts.assign(rq->diags.pt, rq->diags.pt + rq->diags.n_diag);
+      r->item.diags.pt = r->pts.data();
+    } else if (rq->diags.slots) {
+      r->slots.assign(rq->diags.slots, rq->diags.slots + rq->diags.n_diag);
+      r->item.diags.slots = r->slots.data();
+    }
     r->ws_need = rq->sim_ws_bytes;
     r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(S->mu);

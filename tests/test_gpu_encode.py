@@ -1,0 +1,213 @@
+"""Plaintext encoding on the device, and LTs whose diagonals the library
+encodes on the fly, against the oracle.
+
+FP64 rounding decides each integer coefficient of an encoding (Section II-A:
+m = round(scale sigma^-1(z))).  The device's FFT and the oracle's FFT round
+differently in the last bits, so a coefficient whose unrounded value lies
+within that error of a half-integer may round either way.  The checks:
+everywhere else the integers are equal, and there they differ by 1; the
+NTT-form residues equal the oracle's NTT of the device's integers bit for bit;
+an LT with on-the-fly diagonals equals, bit for bit, the oracle's LT given
+the device's encodings of the same (pre-rotated) diagonals; and every result
+decrypts to M v within the stated tolerance."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2605_17222_amd as H
+import workload as W
+from gpu_common import gpu_params, limbs_tensor, log
+from oracle import encoding as E
+
+pytestmark = pytest.mark.gpu
+
+
+def _slots_tensor(z):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(z, dtype=np.complex128)).to("cuda")
+
+
+def _encode(P, prm, zs, rots, scale, first, nl):
+    import torch
+    outs = [H.empty((nl, prm.n)) for _ in zs]
+    coefs = [torch.empty(prm.n, dtype=torch.int64, device="cuda") for _ in zs]
+    wsb = H.ckks_encode_workspace_size(P, len(zs))
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
+    dz = [_slots_tensor(z) for z in zs]
+    H.ckks_encode(P, dz, rots, scale, first, nl, outs, ws, wsb, coefs)
+    torch.cuda.synchronize()
+    return [H.to_host(o) for o in outs], [c.cpu().numpy() for c in coefs]
+
+
+def _check_coefficients(coef, z, rot, scale, n):
+    """Equal to the oracle's rounding except at near-ties (FFT error bound)."""
+    v = E.encode_unrounded(E.rotate_slots(z, rot), scale, n)
+    ref = np.sign(v) * np.floor(np.abs(v) + 0.5)
+    d = coef - ref.astype(np.int64)
+    assert np.abs(d).max() <= 1
+    if np.any(d):
+        # both FFTs are within ~log2(N) ulp of max|v| of the exact value
+        tol = 64 * np.log2(n) * np.finfo(np.float64).eps * np.abs(v).max()
+        frac = np.abs(v[d != 0]) % 1.0
+        assert np.all(np.abs(frac - 0.5) < tol), (frac, tol)
+    return int(np.count_nonzero(d))
+
+
+def _encode_case(prm, count, seed, bases):
+    o = O.Oracle(prm)
+    P = gpu_params(prm)
+    S, scale = prm.slots, 2.0 ** prm.log_delta
+    g = np.random.default_rng(seed)
+    zs = [W.complex_uniform(W.rng(seed, i), S) for i in range(count)]
+    rots = [0, 1, -1, S - 3] + [int(x) for x in g.integers(-S, S, size=count)]
+    rots = rots[:count]
+    ties = 0
+    for first, nl in bases:
+        basis = list(range(first, first + nl))
+        log("encode", prm.log_n, "count", count, "primes", first, "..", first + nl - 1)
+        outs, coefs = _encode(P, prm, zs, rots, scale, first, nl)
+        for z, r, out, coef in zip(zs, rots, outs, coefs):
+            ties += _check_coefficients(coef, z, r, scale, prm.n)
+            # poly_from_signed reduces the integers into each prime and applies the NTT
+            assert np.array_equal(out, o.poly_from_signed(coef, basis))
+            back = E.decode(coef, scale, prm.n)
+            assert np.abs(back - E.rotate_slots(z, r)).max() < 1e-5
+    assert ties <= max(2, count * prm.n // 1000)
+
+
+def test_encode_toy_against_oracle():
+    prm = W.params_toy()
+    K = prm.alpha + prm.max_level + 1
+    _encode_case(prm, 24, 51, [(0, K), (prm.alpha, prm.max_level + 1), (0, prm.alpha + 2)])
+
+
+def test_encode_n16_against_oracle():
+    prm = W.params_n16()
+    K = prm.alpha + prm.max_level + 1
+    _encode_case(prm, 3, 52, [(0, K)])
+
+
+def _th_pre_rotations(split, n, stride, centre, S):
+    n1, n2, _ = split
+    return [-(stride * (n1 * n2 * (t // (n1 * n2)) - centre)) % S for t in range(n)]
+
+
+def _onfly_case(prm, o, keys, level, split, diags_by_t, v, seed, algo="th", stride=1, centre=0, tol=5e-3):
+    """Runs the LT with slot diagonals encoded on the fly and with the device's
+    own encodings as plaintexts; both must equal the oracle's LT given those
+    encodings, and decrypt to M v."""
+    import torch
+    P = gpu_params(prm)
+    S, delta = prm.slots, 2.0 ** prm.log_delta
+    th_split = split if algo == "th" else (1,) + tuple(split)
+    n = int(np.prod(th_split))
+    ts = [t for t in range(n) if diags_by_t.get(t) is not None]
+    pre = _th_pre_rotations(th_split, n, stride, centre, S)
+    K = prm.alpha + prm.max_level + 1
+    enc, _ = _encode(P, prm, [diags_by_t[t] for t in ts], [pre[t] for t in ts], delta, 0, K)
+    pts = [None] * n
+    for t, f in zip(ts, enc):
+        pts[t] = f
+    ct = o.encrypt(level, v, delta, seed=seed)
+    th_keys = {r: keys[r] for r in W.th_rotations(*th_split, stride=stride, centre=centre, slots=S)}
+    log("oracle LT", prm.log_n, "level", level, "split", th_split, "diagonals", len(ts))
+    ref = o.lt_th(level, ct, th_split, pts, th_keys, stride=stride, centre=centre)
+    code = H.CKKS_LT_TH_BSGS if algo == "th" else H.CKKS_LT_DH_BSGS
+    dkeys = {r: limbs_tensor(k) for r, k in th_keys.items()}
+    c0, c1 = limbs_tensor(ct[0]), limbs_tensor(ct[1])
+    dslots = [None if diags_by_t.get(t) is None else _slots_tensor(diags_by_t[t]) for t in range(n)]
+    dpts = [None if f is None else limbs_tensor(f) for f in pts]
+    res = []
+    for onfly, items in ((True, dslots), (False, dpts)):
+        wsb = H.ckks_lt_workspace_size(P, level, split, items, code, stride=stride, centre=centre, onfly=onfly)
+        ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
+        o0, o1 = H.empty((level, prm.n)), H.empty((level, prm.n))
+        log("device LT onfly" if onfly else "device LT plaintexts", "workspace", wsb)
+        lvl, sc = H.ckks_lt_eval(P, level, delta, c0, c1, split, items, delta, dkeys, code, o0, o1, ws, wsb,
+                                 stride=stride, centre=centre, onfly=onfly)
+        torch.cuda.synchronize()
+        res.append((np.stack([H.to_host(o0), H.to_host(o1)]), sc))
+        del ws
+    assert np.array_equal(res[0][0], ref)
+    assert np.array_equal(res[1][0], ref)
+    offs = {(stride * (t - centre)) % S: diags_by_t[t] for t in ts}
+    err = np.abs(o.decrypt_slots(res[0][0], res[0][1]) - W.matvec(offs, v)).max()
+    log("decrypted max error", err)
+    assert err <= tol
+    return res[0][0]
+
+
+def test_onfly_dense_toy_th():
+    # The dense n = N/2 LT of the paper's parameter sets, at the toy ring:
+    # 2048 diagonals, split (16, 16, 8), every plaintext encoded on the fly.
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(61)
+    split = (16, 16, 8)
+    keys = o.rotkeys(W.th_rotations(*split))
+    S = prm.slots
+    diags = W.banded_diagonals(62, S, range(S))
+    _onfly_case(prm, o, keys, prm.max_level, split, {t: diags[t] for t in range(S)}, W.input_vector(63, S), 64)
+
+
+def test_onfly_sparse_progressions_th_dh():
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(71)
+    S = prm.slots
+    g = np.random.default_rng(72)
+    cases = [("th", (2, 4, 4), 1, 0), ("th", (4, 2, 2), 3, 5), ("dh", (4, 8), 16, 7), ("th", (2, 2, 4), 5, 8)]
+    rots = set()
+    for algo, split, stride, centre in cases:
+        th_split = split if algo == "th" else (1,) + split
+        rots |= set(W.th_rotations(*th_split, stride=stride, centre=centre, slots=S))
+    keys = o.rotkeys(sorted(rots))
+    for c, (algo, split, stride, centre) in enumerate(cases):
+        n = int(np.prod(split))
+        present = sorted(set(int(t) for t in g.choice(n, size=n // 2 + 1)))
+        offs = {t: (stride * (t - centre)) % S for t in present}
+        dg = W.banded_diagonals(80 + c, S, sorted(offs.values()))
+        by_t = {t: dg[offs[t]] for t in present}
+        log("case", c, algo, split, "stride", stride, "centre", centre, "present", len(present))
+        _onfly_case(prm, o, keys, 1 + c % prm.max_level, split, by_t, W.input_vector(90 + c, S), 100 + c,
+                    algo=algo, stride=stride, centre=centre)
+
+
+def test_onfly_n16_banded64():
+    # The N = 2^16, level 24, 64-diagonal workload with its plaintexts
+    # encoded on the fly.
+    prm = W.params_n16()
+    o = O.Oracle(prm)
+    o.keygen(111)
+    split = (4, 4, 4)
+    keys = o.rotkeys(W.th_rotations(*split))
+    S = prm.slots
+    diags = W.banded_diagonals(112, S, range(64))
+    _onfly_case(prm, o, keys, 24, split, {t: diags[t] for t in range(64)}, W.input_vector(113, S), 114, tol=1e-4)
+
+
+def test_onfly_through_server_equals_direct():
+    import torch
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(121)
+    split = (2, 2, 4)
+    keys = o.rotkeys(W.th_rotations(*split))
+    S, delta = prm.slots, 2.0 ** prm.log_delta
+    diags = W.banded_diagonals(122, S, range(16))
+    v = W.input_vector(123, S)
+    direct = _onfly_case(prm, o, keys, 2, split, {t: diags[t] for t in range(16)}, v, 124)
+    P = gpu_params(prm)
+    ct = o.encrypt(2, v, delta, seed=124)
+    c0, c1 = limbs_tensor(ct[0]), limbs_tensor(ct[1])
+    dslots = [_slots_tensor(diags[t]) for t in range(16)]
+    o0, o1 = H.empty((2, prm.n)), H.empty((2, prm.n))
+    torch.cuda.synchronize()
+    with H.Server(1 << 28, max_batch=2, max_inflight=1) as srv:
+        ring = H.ckks_server_add_ring(srv, P, {r: limbs_tensor(k) for r, k in keys.items()})
+        rid = H.ckks_server_submit(srv, ring, 2, delta, c0, c1, split, dslots, delta, o0, o1, onfly=True)
+        H.ckks_server_wait_all(srv)
+        status, _ = H.ckks_server_poll(srv, rid)
+        assert status == H.CKKS_OK, H.strerror(status)
+    got = np.stack([H.to_host(o0), H.to_host(o1)])
+    assert np.array_equal(got, direct)
