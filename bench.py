@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="Poisson serving run length (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--no-chain", action="store_true", help="skip the DFT-like chain")
+    ap.add_argument("--dense-steps", type=int, default=2,
+                    help="timed steps of the dense n = N/2 LT with on-the-fly plaintexts (0: skip)")
     return ap.parse_args()
 
 
@@ -85,7 +87,7 @@ def events_ms(torch, stream, fn, reps):
     return e0.elapsed_time(e1), time.perf_counter() - t0
 
 
-def make_inputs(P, prm, level, split, algo, seed, torch, H):
+def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True):
     """Uniform residues on the device for the ciphertext, keys and plaintexts."""
     import workload as W
     n = prm.n
@@ -113,8 +115,58 @@ def make_inputs(P, prm, level, split, algo, seed, torch, H):
     keys = {}
     for r in rots:
         keys[r] = residues(pq[:kmax] * (2 * beta_max)).view(beta_max, 2, kmax, n)
-    pts = [residues(pt_mods) for _ in range(n_pt)]
+    pts = [residues(pt_mods) for _ in range(n_pt)] if with_pts else []
     return c0, c1, keys, pts
+
+
+def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99):
+    """TH-BSGS LT whose diagonals (offsets 0 .. n_diag-1, complex uniform
+    [-1, 1] slot vectors resident on the device) the library encodes right
+    before each multiply-accumulate; keys and ciphertext uniform residues.
+    One extra step with every kernel timed gives the breakdown."""
+    S, n = prm.slots, prm.n
+    c0, c1, keys, _ = make_inputs(P, prm, level, split, "th", 4321, torch, H, with_pts=False)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    z = torch.empty((n_diag, S), dtype=torch.complex128, device="cuda")
+    zr = torch.view_as_real(z)
+    for t0 in range(0, n_diag, 1024):
+        zr[t0:t0 + 1024].uniform_(-1.0, 1.0, generator=g)
+    slots = [z[t] for t in range(n_diag)]
+    code = H.CKKS_LT_TH_BSGS
+    ws_bytes = H.ckks_lt_workspace_size(P, level, split, slots, code, onfly=True)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out0, out1 = H.empty((level, n)), H.empty((level, n))
+    delta = 2.0 ** prm.log_delta
+    stream = torch.cuda.current_stream()
+
+    def step():
+        H.ckks_lt_eval(P, level, delta, c0, c1, split, slots, delta, keys, code, out0, out1, ws, ws_bytes, stream,
+                       onfly=True)
+
+    for _ in range(warmup):
+        step()
+    ms, wall = events_ms(torch, stream, step, steps)
+    all_mask = (1 << len(H.KERNELS)) - 1
+    H.ckks_profile_enable(all_mask)
+    step()
+    torch.cuda.synchronize()
+    prof = {name: H.ckks_profile_read(k) for k, name in enumerate(H.KERNELS)}
+    H.ckks_profile_enable(0)
+    K = prm.alpha + level + 1
+    beta_max = -(-(prm.max_level + 1) // prm.alpha)
+    kmax = prm.alpha + prm.max_level + 1
+    key_bytes = len(keys) * beta_max * 2 * kmax * n * 8
+    res = {"split": list(split), "n_diag": n_diag, "level": level, "keys": len(keys),
+           "ms_per_lt": round(ms / steps, 3), "lt_per_s": round(steps / wall, 3),
+           "plaintexts_encoded_per_s": round(n_diag * steps / wall, 1),
+           "slot_bytes": z.numel() * 16, "key_bytes": key_bytes,
+           "resident_plaintext_bytes_avoided": n_diag * K * n * 8, "workspace_bytes": ws_bytes,
+           "kernels_ms_per_lt": {k: round(v[1], 3) for k, v in prof.items() if v[0]},
+           "recipe": "diagonals complex U[-1,1] on the device (seed %d), keys and ciphertext uniform residues" % seed}
+    del ws, z, slots, keys
+    torch.cuda.empty_cache()
+    return res
 
 
 def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0):
@@ -151,6 +203,30 @@ def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0)
                 prof[name] = H.ckks_profile_read(k)
         H.ckks_profile_enable(0)
     return wall, ms_events, prof, ws_bytes
+
+
+# The paper's FPGA latency for its dense LTs (its design, Set-A/B/C): context
+# for the same shapes here, not a like-for-like target.
+PAPER_FPGA_MS = {"A": 19.44, "B": 726.59, "C": 3113.70}
+
+
+def paper_sets_leg(steps, torch, H):
+    """Dense n = N/2 TH-BSGS LTs at the paper's Set-A/B/C parameters (54-bit
+    primes, its splits), top level, diagonals encoded on the fly."""
+    import workload as W
+    res = {}
+    for name in "ABC":
+        prm = W.params_paper_set(name)
+        split = W.PAPER_SETS[name]["split"]
+        P = H.ckks_params_create(prm.log_n, prm.q, prm.p, prm.dnum)
+        r = onfly_leg(P, prm, prm.max_level, split, prm.slots, steps, 1, torch, H)
+        r["N"] = prm.n
+        r["alpha"] = prm.alpha
+        r["paper_fpga_ms"] = PAPER_FPGA_MS[name]
+        res["set_" + name] = r
+        del P
+        print("set %s done" % name, flush=True, file=sys.stderr)
+    return res
 
 
 def compulsory_bytes(prm, level, split, algo):
@@ -502,6 +578,16 @@ def main():
     if not args.no_chain:
         out["dft_chain"] = chain_leg(P, prm, 10, torch, H)
         print("chain leg done", flush=True, file=sys.stderr)
+    # the same workload with its 64 plaintexts encoded on the fly, and the
+    # dense n = N/2 LT (every diagonal present) that on-the-fly encoding makes
+    # fit on one device, at the largest parameter set's TH split (32, 32, 32)
+    out["onfly_banded64"] = onfly_leg(P, prm, level, th_split, 64, args.steps, 2, torch, H)
+    print("on-the-fly banded leg done", flush=True, file=sys.stderr)
+    if args.dense_steps > 0:
+        out["onfly_dense"] = onfly_leg(P, prm, level, (32, 32, 32), prm.slots, args.dense_steps, 1, torch, H)
+        print("dense leg done", flush=True, file=sys.stderr)
+        out["paper_sets"] = paper_sets_leg(args.dense_steps, torch, H)
+        print("paper sets leg done", flush=True, file=sys.stderr)
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(args.serve_seconds, args.serve_rate, torch, H)
         print("serving leg done", flush=True, file=sys.stderr)

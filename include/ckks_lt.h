@@ -58,15 +58,17 @@ const char* ckks_strerror(int code);
 /*
  * RNS-CKKS parameters (Section II-A): ring Z[X]/(X^N + 1), ciphertext modulus
  * Q = q_0 ... q_L, special modulus P = p_0 ... p_{alpha-1} for the
- * generalized key switching of Fig. 1, with alpha = ceil((L+1)/dnum).
+ * generalized key switching of Fig. 1.  A digit is a group of alpha
+ * consecutive q primes, so there are dnum = beta = ceil((L+1)/alpha) digits
+ * at the top level (the paper's Set-C has L+1 = 32, alpha = 12, beta = 3).
  */
 typedef struct {
-  int log_n;            /* log2 N, 8 <= log_n <= 16                          */
+  int log_n;            /* log2 N, 12 <= log_n <= 16                         */
   int n_q;              /* L + 1                                             */
   const uint64_t* q;    /* host [n_q]: q_0 .. q_L                            */
-  int n_p;              /* alpha; must equal ceil(n_q / dnum)                */
+  int n_p;              /* alpha                                             */
   const uint64_t* p;    /* host [n_p]: p_0 .. p_{alpha-1}                    */
-  int dnum;             /* number of key-switching digits at the top level   */
+  int dnum;             /* digits at the top level; must equal ceil(n_q/n_p) */
   const uint64_t* psi;  /* host [n_p + n_q] (P first) primitive 2N-th roots,
                            or NULL: then psi = g^((q-1)/2N) for the smallest
                            quadratic non-residue g >= 2 of each prime        */
@@ -469,8 +471,7 @@ int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int 
 #define CKKS_KERNEL_AUTOMORPH 7
 #define CKKS_KERNEL_KEYSWITCH_GATHER 8
 #define CKKS_KERNEL_ENCODE_FFT 9  /* plaintext encoding: the two FFT passes  */
-#define CKKS_KERNEL_ENCODE_RNS 10 /* plaintext encoding: residues of m      */
-#define CKKS_KERNEL_COUNT 11
+#define CKKS_KERNEL_COUNT 10
 
 /*
  * Process-wide: for every kernel k with bit (1 << k) set in mask, each later

@@ -672,7 +672,7 @@ void* orc_ctx_create(int logn, int nq, const uint64_t* q, int np, const uint64_t
     if (logn < 2 || logn > 17) throw std::runtime_error("bad log_n");
     Ctx* c = new Ctx;
     c->logn = logn; c->n = 1 << logn; c->L = nq - 1; c->alpha = np; c->dnum = dnum;
-    if ((nq + dnum - 1) / dnum != np) { delete c; throw std::runtime_error("alpha != ceil((L+1)/dnum)"); }
+    if ((nq + np - 1) / np != dnum) { delete c; throw std::runtime_error("dnum != ceil((L+1)/alpha)"); }
     std::vector<uint64_t> all;
     for (int i = 0; i < np; ++i) all.push_back(p[i]);
     for (int j = 0; j < nq; ++j) all.push_back(q[j]);

@@ -47,7 +47,7 @@ EXPORTED = [
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
-           "automorph", "keyswitch_gather", "encode_fft", "encode_rns"]
+           "automorph", "keyswitch_gather", "encode_fft"]
 
 
 class CkksError(RuntimeError):

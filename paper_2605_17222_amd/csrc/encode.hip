@@ -1,6 +1,6 @@
 // Plaintext encoding on the device (Section II-A): the integer polynomial
-// m = round(scale * sigma^-1(z)) of a vector z of N/2 complex slots, reduced
-// into a range of primes and brought to NTT form.
+// m = round(scale * sigma^-1(z)) of a vector z of N/2 complex slots (the
+// forward NTT then reduces m into each prime as its first pass reads it).
 //
 // Slot t is m(zeta^(5^t)), zeta = e^(i pi / N).  With e_t = 5^t mod 2N = 4 j_t + 1
 // (5^t is 1 mod 4, and t -> j_t permutes [0, N/2)) and u_k = m_k + i m_(k+N/2),
@@ -117,28 +117,6 @@ __global__ void __launch_bounds__(256) enc_pass2(EncArgs a, const double* __rest
   }
 }
 
-// Signed coefficients -> residues of n limbs (coefficient domain).
-__global__ void __launch_bounds__(256) enc_rns(RnsArgs a, const PrimeDev* __restrict__ primes, int log_n) {
-  const int it = blockIdx.y;
-  const size_t n = (size_t)1 << log_n;
-  const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t m = a.coef[it][k];
-  const double md = (double)m;
-  uint64_t* __restrict__ out = a.out[it];
-  const int p0 = a.prime0[it];
-  for (int l = 0; l < a.nlimbs[it]; ++l) {
-    const PrimeDev& pr = primes[p0 + l];
-    const int64_t q = (int64_t)pr.q;
-    // |m / q| < 2^33, so the estimated quotient is within one of the true
-    // floor and r lands in [-q, 2q).
-    const int64_t quo = (int64_t)floor(md * pr.qinv_d);
-    int64_t r = m - quo * q;
-    r = r < 0 ? r + q : r;
-    r = r >= q ? r - q : r;
-    out[(size_t)l * n + k] = (uint64_t)r;
-  }
-}
-
 template <int LOGA, int LOGB>
 hipError_t launch_enc(const ckks_params* P, const EncArgs& a, hipStream_t s) {
   constexpr int A = 1 << LOGA, B = 1 << LOGB;
@@ -169,15 +147,6 @@ hipError_t launch_encode_fft(const ckks_params* P, const EncArgs& a, hipStream_t
     case 16: return launch_enc<8, 7>(P, a, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_encode_rns(const ckks_params* P, const RnsArgs& a, hipStream_t s) {
-  if (a.count <= 0) return hipSuccess;
-  double words = 0;
-  for (int i = 0; i < a.count; ++i) words += 1.0 + a.nlimbs[i];
-  ProfScope prof(CKKS_KERNEL_ENCODE_RNS, s, words * P->n * 8);
-  hipLaunchKernelGGL(enc_rns, dim3(P->n / 256, a.count), dim3(256), 0, s, a, P->d_primes, P->log_n);
-  return hipGetLastError();
 }
 
 }  // namespace ckks

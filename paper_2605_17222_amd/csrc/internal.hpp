@@ -80,6 +80,11 @@ struct LimbRange {
   const uint64_t* sinv_sh;  // Shoup companion (device, inside a BConvPlan)
   int prime0;
   int count;
+  // Forward transforms: in holds N signed 64-bit coefficients shared by every
+  // limb of the range, reduced into each limb's prime as the first pass reads
+  // them (|coefficient| < 2^62).
+  int signed_in;
+  int pad;
 };
 
 constexpr int kMaxRanges = 16;
@@ -179,14 +184,6 @@ struct EncArgs {
   double* y[kMaxEnc];
   int64_t* coef[kMaxEnc];
 };
-// Signed coefficients coef[i] -> residues out[i] + l N of primes prime0[i] + l.
-struct RnsArgs {
-  int count;
-  const int64_t* coef[kMaxEnc];
-  uint64_t* out[kMaxEnc];
-  int prime0[kMaxEnc];
-  int nlimbs[kMaxEnc];
-};
 
 // Kernel launchers.
 hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
@@ -197,7 +194,6 @@ hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGather
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
 hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
 hipError_t launch_encode_fft(const struct ::ckks_params* P, const EncArgs& a, hipStream_t s);
-hipError_t launch_encode_rns(const struct ::ckks_params* P, const RnsArgs& a, hipStream_t s);
 
 }  // namespace ckks
 

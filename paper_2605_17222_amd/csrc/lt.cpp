@@ -54,6 +54,8 @@ LimbRange range(const uint64_t* in, uint64_t* out, int prime0, int count, const 
   r.sinv_sh = sinv_sh;
   r.prime0 = prime0;
   r.count = count;
+  r.signed_in = 0;
+  r.pad = 0;
   return r;
 }
 
@@ -293,17 +295,16 @@ struct EncItem {
   int64_t* coef;
 };
 
-// FFT passes, residues and forward NTTs of up to kMaxEnc items per launch.
+// FFT passes and forward NTTs (from the signed integers) of up to kMaxEnc
+// items per launch.
 void encode(Run& R, const std::vector<EncItem>& items) {
   const long S = R.P->n / 2;
   for (size_t i0 = 0; i0 < items.size(); i0 += kMaxEnc) {
     const size_t mark = R.ws.mark();
     const int cnt = (int)std::min<size_t>(kMaxEnc, items.size() - i0);
     EncArgs ea;
-    RnsArgs ra;
     memset(&ea, 0, sizeof(ea));
-    memset(&ra, 0, sizeof(ra));
-    ea.count = ra.count = cnt;
+    ea.count = cnt;
     for (int c = 0; c < cnt; ++c) {
       const EncItem& it = items[i0 + c];
       ea.z[c] = it.z;
@@ -311,18 +312,16 @@ void encode(Run& R, const std::vector<EncItem>& items) {
       ea.scale[c] = it.scale;
       ea.y[c] = reinterpret_cast<double*>(R.limbs(1));  // N/2 complex values
       ea.coef[c] = it.coef ? it.coef : reinterpret_cast<int64_t*>(R.limbs(1));
-      ra.coef[c] = ea.coef[c];
-      ra.out[c] = it.out;
-      ra.prime0[c] = it.first_prime;
-      ra.nlimbs[c] = it.n_limbs;
     }
     if (R.live()) {
       R.check(launch_encode_fft(R.P, ea, R.s));
-      if (R.live()) R.check(launch_encode_rns(R.P, ra, R.s));
+      // the NTT's first pass reduces the integers into each prime itself
       NttBatch fwd(R, true);
       for (int c = 0; c < cnt; ++c) {
         const EncItem& it = items[i0 + c];
-        fwd.add(range(it.out, it.out, it.first_prime, it.n_limbs));
+        LimbRange r = range(reinterpret_cast<const uint64_t*>(ea.coef[c]), it.out, it.first_prime, it.n_limbs);
+        r.signed_in = 1;
+        fwd.add(r);
       }
     }
     R.ws.reset(mark);

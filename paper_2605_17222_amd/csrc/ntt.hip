@@ -58,7 +58,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   const int n = 1 << log_n;
   const uint64_t* __restrict__ tw = pr.tw + (FWD ? 0 : 2 * (size_t)n);
   const bool first = (COL == FWD);  // first pass of the transform
-  const uint64_t* __restrict__ src = (first ? R.in : R.out) + (size_t)limb * n;
+  const uint64_t* __restrict__ src = (first ? R.in : R.out) + (FWD && first && R.signed_in ? 0 : (size_t)limb * n);
   uint64_t* __restrict__ dst = R.out + (size_t)limb * n;
 
   const int tid = threadIdx.x;
@@ -191,8 +191,23 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   };
 
   if (FWD) {
+    if (first && R.signed_in) {
+      // signed coefficients -> residues: |m / q| < 2^33, so the estimated
+      // quotient is within one of the floor and r lands in [-q, 2q)
+      const int64_t* __restrict__ sc = reinterpret_cast<const int64_t*>(src);
+      const int64_t qs = (int64_t)q;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(src + addr(j + T * u));
+      for (int u = 0; u < 16; ++u) {
+        const int64_t m = sc[addr(j + T * u)];
+        int64_t r = m - (int64_t)floor((double)m * qi) * qs;
+        r = r < 0 ? r + qs : r;
+        r = r >= qs ? r - qs : r;
+        v[u] = (uint64_t)r;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(src + addr(j + T * u));
+    }
     if (first) convert_in();
     round1();
     recentre();

@@ -153,7 +153,7 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
   if (!d || !out || !d->q || !d->p) return CKKS_E_INVALID_ARG;
   *out = nullptr;
   if (d->log_n < 12 || d->log_n > 16 || d->n_q < 1 || d->n_p < 1 || d->dnum < 1) return CKKS_E_INVALID_ARG;
-  if ((d->n_q + d->dnum - 1) / d->dnum != d->n_p) return CKKS_E_INVALID_ARG;
+  if ((d->n_q + d->n_p - 1) / d->n_p != d->dnum) return CKKS_E_INVALID_ARG;  // digits of alpha primes
   if (d->n_q + d->n_p > kMaxDst) return CKKS_E_UNSUPPORTED;
   ckks_params* P = new ckks_params;
   Cleanup<ckks_params> guard(P);

@@ -211,3 +211,22 @@ def test_onfly_through_server_equals_direct():
         assert status == H.CKKS_OK, H.strerror(status)
     got = np.stack([H.to_host(o0), H.to_host(o1)])
     assert np.array_equal(got, direct)
+
+
+def test_onfly_dense_paper_set_a():
+    # The paper's Set-A (N = 2^13, L+1 = 5, alpha = 5, 54-bit primes) with its
+    # dense n = N/2 = 4096 LT and split (16, 16, 16), at the top level.
+    prm = W.params_paper_set("A")
+    split = W.PAPER_SETS["A"]["split"]
+    o = O.Oracle(prm)
+    o.keygen(131)
+    keys = o.rotkeys(W.th_rotations(*split))
+    S = prm.slots
+    diags = W.banded_diagonals(132, S, range(S))
+    # Tolerance: with one digit (beta = 1) a key switch adds about N sigma per
+    # coefficient (the digit is as large as P), ~N^1.5 sigma = 2^21 in a slot,
+    # i.e. 2^-19 at Delta = 2^40 per rotated ciphertext; the MAC sums 4096 of
+    # them with unit-size weights, ~64 * 2^-19 = 1.2e-4 rms, and the maximum
+    # over 4096 slots stays below 5e-3.
+    _onfly_case(prm, o, keys, prm.max_level, split, {t: diags[t] for t in range(S)}, W.input_vector(133, S), 134,
+                tol=5e-3)

@@ -53,7 +53,7 @@ def test_params_create_rejects_bad_input_without_gpu():
     _lib_path()
     prm = W.params_toy()
     with pytest.raises(H.CkksError) as e:
-        H.ckks_params_create(prm.log_n, prm.q, prm.p, 2)   # alpha != ceil((L+1)/dnum)
+        H.ckks_params_create(prm.log_n, prm.q, prm.p, 2)   # dnum != ceil((L+1)/alpha)
     assert e.value.code == H.CKKS_E_INVALID_ARG
     with pytest.raises(H.CkksError):
         H.ckks_params_create(prm.log_n, (prm.q[0], prm.q[1], prm.q[1]), prm.p, 3)  # duplicate prime

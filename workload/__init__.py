@@ -127,6 +127,26 @@ def params_n16(log_n: int = 16) -> Params:
                   dnum=3, log_delta=40, h=192)
 
 
+# The paper's evaluation sets (N, L+1, alpha, beta; w = 54-bit words) with the
+# dense LT dimension n = N/2 and the TH-BSGS split of its parameter table.
+PAPER_SETS = {
+    "A": dict(log_n=13, n_q=5, alpha=5, dnum=1, split=(16, 16, 16)),
+    "B": dict(log_n=15, n_q=16, alpha=8, dnum=2, split=(32, 16, 32)),
+    "C": dict(log_n=16, n_q=32, alpha=12, dnum=3, split=(32, 32, 32)),
+}
+
+
+def params_paper_set(name: str) -> Params:
+    """Set-A/B/C: every prime 54 bits and 1 mod 2N (N of the set), Delta =
+    2^40, h = 192.  alpha special primes; the digits have alpha primes each
+    (beta = ceil((L+1)/alpha) = dnum)."""
+    s = PAPER_SETS[name]
+    two_n = 1 << (s["log_n"] + 1)
+    p54 = ntt_primes(54, s["n_q"] + s["alpha"], two_n)
+    return Params(log_n=s["log_n"], q=tuple(p54[:s["n_q"]]), p=tuple(p54[s["n_q"]:]), dnum=s["dnum"],
+                  log_delta=40, h=192)
+
+
 # ----------------------------------------------------------------------------
 # Splits (n1', n2', n3') and rotation sets
 # ----------------------------------------------------------------------------
