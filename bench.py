@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-chain", action="store_true", help="skip the DFT-like chain")
     ap.add_argument("--dense-steps", type=int, default=2,
                     help="timed steps of the dense n = N/2 LT with on-the-fly plaintexts (0: skip)")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="only the dense on-the-fly LT at N=2^16 (for rocprofv3); prints its JSON")
     return ap.parse_args()
 
 
@@ -507,6 +509,10 @@ def main():
     level = 24
     th_split, bs_split = (4, 4, 4), (8, 8)
     P = H.ckks_params_create(prm.log_n, prm.q, prm.p, prm.dnum)
+    if args.dense_only:
+        r = onfly_leg(P, prm, level, (32, 32, 32), prm.slots, max(1, args.dense_steps), 1, torch, H)
+        print(json.dumps({"onfly_dense": r}), flush=True)
+        return
     if args.profile_only:
         # calibration for the HBM byte counters: a plain 256 MiB device copy
         src = torch.empty(32 << 20, dtype=torch.int64, device="cuda").fill_(1)

@@ -47,7 +47,9 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 __device__ __forceinline__ double as_d(uint64_t u) { return __longlong_as_double((long long)u); }
 __device__ __forceinline__ uint64_t as_u(double d) { return (uint64_t)__double_as_longlong(d); }
 
-template <int PLOG, int G, bool COL, bool FWD, bool FP>
+// SIN (forward column pass only): the input is the range's shared signed
+// coefficients (LimbRange::signed_in).
+template <int PLOG, int G, bool COL, bool FWD, bool FP, bool SIN>
 __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const PrimeDev& pr, int log_n, int epi,
                                          uint64_t* lds) {
   constexpr int P = 1 << PLOG;
@@ -58,7 +60,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   const int n = 1 << log_n;
   const uint64_t* __restrict__ tw = pr.tw + (FWD ? 0 : 2 * (size_t)n);
   const bool first = (COL == FWD);  // first pass of the transform
-  const uint64_t* __restrict__ src = (first ? R.in : R.out) + (FWD && first && R.signed_in ? 0 : (size_t)limb * n);
+  const uint64_t* __restrict__ src = (first ? R.in : R.out) + (SIN ? 0 : (size_t)limb * n);
   uint64_t* __restrict__ dst = R.out + (size_t)limb * n;
 
   const int tid = threadIdx.x;
@@ -191,7 +193,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   };
 
   if (FWD) {
-    if (first && R.signed_in) {
+    if constexpr (SIN) {
       // signed coefficients -> residues: |m / q| < 2^33, so the estimated
       // quotient is within one of the floor and r lands in [-q, 2q)
       const int64_t* __restrict__ sc = reinterpret_cast<const int64_t*>(src);
@@ -281,7 +283,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   }
 }
 
-template <int PLOG, int G, bool COL, bool FWD>
+template <int PLOG, int G, bool COL, bool FWD, bool SIN>
 __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
     ntt_pass(NttArgs args, const PrimeDev* __restrict__ primes, int log_n, int epi) {
   constexpr int P = 1 << PLOG;
@@ -297,9 +299,9 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
   const LimbRange& R = args.r[ri];
   const PrimeDev& pr = primes[R.prime0 + limb];
   if (pr.fp)
-    ntt_body<PLOG, G, COL, FWD, true>(R, limb, pr, log_n, epi, lds);
+    ntt_body<PLOG, G, COL, FWD, true, SIN>(R, limb, pr, log_n, epi, lds);
   else
-    ntt_body<PLOG, G, COL, FWD, false>(R, limb, pr, log_n, epi, lds);
+    ntt_body<PLOG, G, COL, FWD, false, SIN>(R, limb, pr, log_n, epi, lds);
 }
 
 template <int PLOG, bool COL, bool FWD>
@@ -315,9 +317,21 @@ hipError_t launch_pass(const ckks_params* P, const NttArgs& a, int total, int ep
   double words = (double)total * n * (epi == EPI_SUBMUL ? 3 : 2);
   if (!FWD && !COL)
     for (int i = 0; i < a.nr; ++i) words += a.r[i].copy ? (double)a.r[i].count * n : 0;
+  // signed input: every range of the launch, forward transforms only
+  const bool sin = a.r[0].signed_in != 0;
+  for (int i = 1; i < a.nr; ++i)
+    if ((a.r[i].signed_in != 0) != sin) return hipErrorInvalidValue;
+  if (sin && !FWD) return hipErrorInvalidValue;
   ProfScope prof(id, s, words * 8);
-  hipLaunchKernelGGL((ntt_pass<PLOG, G, COL, FWD>), grid, dim3(G * Pn / 16), 0, s, a, P->d_primes, P->log_n,
-                     epi);
+  if constexpr (COL && FWD) {
+    if (sin) {
+      hipLaunchKernelGGL((ntt_pass<PLOG, G, COL, FWD, true>), grid, dim3(G * Pn / 16), 0, s, a, P->d_primes,
+                         P->log_n, epi);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((ntt_pass<PLOG, G, COL, FWD, false>), grid, dim3(G * Pn / 16), 0, s, a, P->d_primes,
+                     P->log_n, epi);
   return hipGetLastError();
 }
 

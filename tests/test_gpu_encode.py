@@ -230,3 +230,36 @@ def test_onfly_dense_paper_set_a():
     # over 4096 slots stays below 5e-3.
     _onfly_case(prm, o, keys, prm.max_level, split, {t: diags[t] for t in range(S)}, W.input_vector(133, S), 134,
                 tol=5e-3)
+
+
+def test_encode_and_onfly_argument_errors():
+    import torch
+    prm = W.params_toy()
+    P = gpu_params(prm)
+    S, delta = prm.slots, 2.0 ** prm.log_delta
+    K = prm.alpha + prm.max_level + 1
+    z = _slots_tensor(W.complex_uniform(W.rng(5, 0), S))
+    out = H.empty((K, prm.n))
+    wsb = H.ckks_encode_workspace_size(P, 1)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
+    H.ckks_encode(P, [], [], delta, 0, K, [], ws, wsb)  # nothing to do
+    for scale, first, nl in ((0.0, 0, K), (-1.0, 0, K), (float("inf"), 0, K), (delta, 0, K + 1), (delta, -1, 2),
+                             (delta, 0, 0)):
+        with pytest.raises(H.CkksError) as e:
+            H.ckks_encode(P, [z], [0], scale, first, nl, [out], ws, wsb)
+        assert e.value.code == H.CKKS_E_INVALID_ARG
+    with pytest.raises(H.CkksError) as e:
+        H.ckks_encode(P, [z], [0], delta, 0, K, [out], ws, 0)
+    assert e.value.code == H.CKKS_E_WORKSPACE
+    # slot diagonals: TH-/DH-BSGS only; pt and slots together are refused
+    for algo, code in ((H.CKKS_LT_BSGS, H.CKKS_E_UNSUPPORTED), (H.CKKS_LT_NAIVE, H.CKKS_E_UNSUPPORTED)):
+        with pytest.raises(H.CkksError) as e:
+            H.ckks_lt_workspace_size(P, 1, (2, 2), [z] * 4, algo, onfly=True)
+        assert e.value.code == code
+    d, keep = H._diags((2, 2, 1), [z] * 4, delta, onfly=True)
+    d.pt = d.slots
+    import ctypes
+    n = ctypes.c_size_t()
+    assert H.lib().ckks_lt_workspace_size(P, 1, ctypes.byref(d), H.CKKS_LT_TH_BSGS, ctypes.byref(n)) == \
+        H.CKKS_E_INVALID_ARG
+    torch.cuda.synchronize()
