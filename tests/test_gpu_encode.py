@@ -263,3 +263,70 @@ def test_encode_and_onfly_argument_errors():
     assert H.lib().ckks_lt_workspace_size(P, 1, ctypes.byref(d), H.CKKS_LT_TH_BSGS, ctypes.byref(n)) == \
         H.CKKS_E_INVALID_ARG
     torch.cuda.synchronize()
+
+
+def test_onfly_mixed_ragged_batch_and_graph():
+    # One ragged batch: items with resident plaintexts and items whose
+    # diagonals are encoded on the fly, at different levels and splits.  Each
+    # item equals its evaluation alone (and the oracle given the device's
+    # encodings); the batch captured in a HIP graph replays to the same bytes.
+    import torch
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(141)
+    S, delta = prm.slots, 2.0 ** prm.log_delta
+    K = prm.alpha + prm.max_level + 1
+    P = gpu_params(prm)
+    specs = [(2, 16, (2, 2, 4), True), (1, 12, (4, 1, 4), False), (2, 30, (2, 4, 4), True), (1, 5, (1, 4, 2), False)]
+    rots = set()
+    for _, _, split, _ in specs:
+        rots |= set(W.th_rotations(*split))
+    keys = o.rotkeys(sorted(rots))
+    dkeys = {r: limbs_tensor(k) for r, k in keys.items()}
+    batch, refs, keep = [], [], []
+    for i, (level, nd, split, onfly) in enumerate(specs):
+        diags = W.banded_diagonals(150 + i, S, range(nd))
+        v = W.input_vector(160 + i, S)
+        ct = o.encrypt(level, v, delta, seed=170 + i)
+        n = int(np.prod(split))
+        pre = _th_pre_rotations(split, n, 1, 0, S)
+        enc, _ = _encode(P, prm, [diags[t] for t in range(nd)], [pre[t] for t in range(nd)], delta, 0, K)
+        pts = enc + [None] * (n - nd)
+        refs.append(o.lt_th(level, ct, split, pts, keys))
+        c0, c1 = limbs_tensor(ct[0]), limbs_tensor(ct[1])
+        items = [_slots_tensor(diags[t]) for t in range(nd)] if onfly else [limbs_tensor(f) for f in enc]
+        keep += [c0, c1, items]
+        batch.append(H.BatchItem(level, delta, c0, c1, split, items, delta, dkeys, H.empty((level, prm.n)),
+                                 H.empty((level, prm.n)), onfly=onfly))
+    wsb = H.ckks_lt_batch_workspace_size(P, batch, H.CKKS_LT_TH_BSGS)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+    def outputs():
+        return [np.stack([H.to_host(b.out0), H.to_host(b.out1)]) for b in batch]
+
+    log("mixed batch, workspace", wsb)
+    assert H.ckks_lt_eval_batch(P, batch, H.CKKS_LT_TH_BSGS, ws, wsb) == H.CKKS_OK
+    torch.cuda.synchronize()
+    eager = outputs()
+    for i, (e, ref) in enumerate(zip(eager, refs)):
+        assert batch[i].status == H.CKKS_OK
+        assert np.array_equal(e, ref), i
+    log("capture")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            code = H.ckks_lt_eval_batch(P, batch, H.CKKS_LT_TH_BSGS, ws, wsb, torch.cuda.current_stream())
+    assert code == H.CKKS_OK
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        log("replay", rep)
+        for b in batch:
+            b.out0.fill_(7)
+            b.out1.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for e, x in zip(eager, outputs()):
+            assert np.array_equal(e, x), rep
