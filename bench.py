@@ -121,6 +121,36 @@ def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True):
     return c0, c1, keys, pts
 
 
+def step_percentiles(P, prm, level, split, reps, torch, H):
+    """Each of `reps` steps bracketed by its own HIP events: p10/p50/p90 ms."""
+    c0, c1, keys, pts = make_inputs(P, prm, level, split, "th", 1234, torch, H)
+    code = H.CKKS_LT_TH_BSGS
+    ws_bytes = H.ckks_lt_workspace_size(P, level, split, pts, code)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    out0, out1 = H.empty((level, prm.n)), H.empty((level, prm.n))
+    delta = 2.0 ** prm.log_delta
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for _ in range(3):
+        H.ckks_lt_eval(P, level, delta, c0, c1, split, pts, delta, keys, code, out0, out1, ws, ws_bytes, stream)
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        H.ckks_lt_eval(P, level, delta, c0, c1, split, pts, delta, keys, code, out0, out1, ws, ws_bytes, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    pick = lambda f: round(ms[min(reps - 1, int(f * reps))], 4)
+    del ws, keys, pts
+    return {"steps": reps, "p10_ms": pick(0.1), "p50_ms": pick(0.5), "p90_ms": pick(0.9)}
+
+
+# Measured on MI355X with a multiply-add probe: a Shoup modular multiplication
+# (64-bit) issues at about 1.2 T/s over the whole device (v_mad_u64_u32 and
+# FP64 FMA both run at about 30 T/s).
+SHOUP_PEAK_T_PER_S = 1.2
+
+
 def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99):
     """TH-BSGS LT whose diagonals (offsets 0 .. n_diag-1, complex uniform
     [-1, 1] slot vectors resident on the device) the library encodes right
@@ -551,6 +581,19 @@ def main():
                      "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}
                  for k, v in prof.items() if v[0]}
     comp = compulsory_bytes(prm, level, th_split, "th")
+    # the VALU side (NTT, BConv): the operation-count model's modular
+    # multiplications against the measured Shoup rate, and the NTT butterflies
+    # against the NTT passes' own time
+    cost = H.ckks_lt_cost_model(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, th_split)
+    ntt_ms = sum(breakdown[k]["ms_per_step"] for k in breakdown if k.startswith("ntt_"))
+    butterflies = cost["ntt_limbs"] * (prm.n // 2) * prm.log_n
+    valu = {"modmul_per_lt": cost["modmul"], "modmul_T_per_s": round(cost["modmul"] / (ms_step * 1e-3) / 1e12, 3),
+            "peak_T_per_s": SHOUP_PEAK_T_PER_S,
+            "frac": round(cost["modmul"] / (ms_step * 1e-3) / 1e12 / SHOUP_PEAK_T_PER_S, 3),
+            "ntt_butterflies_per_lt": butterflies, "ntt_ms_per_lt": round(ntt_ms, 4),
+            "ntt_T_butterflies_per_s": round(butterflies / (ntt_ms * 1e-3) / 1e12, 3),
+            "note": "modmul from the operation-count model (Table I conventions) over the whole step; peak from a "
+                    "multiply-add probe on this device"}
     out = {
         "metric": METRIC, "value": round(lt_s, 2), "unit": "LT/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -564,7 +607,9 @@ def main():
         "th_vs_bsgs_speedup": round(bs_ms / ms_step, 3),
         "workspace_bytes": ws_bytes,
         "roofline": roofline,
+        "valu": valu,
         "kernels": breakdown,
+        "step_ms": step_percentiles(P, prm, level, th_split, 100, torch, H),
     }
     # the split the library's autotuner picks for this workload, timed the same way
     at_split, at_pred = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, 64)
