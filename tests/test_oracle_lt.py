@@ -144,3 +144,53 @@ def test_dh_counts_table1(toy, split):
     c = o.counters()
     assert c["decompose"] == n2 and c["moddown"] == n2 + 1 and c["keys"] == n1 + n2 - 2
     assert np.abs(_decode(o, out, w, delta) - W.matvec(w.diags, w.vector)).max() <= 5e-3
+
+
+def test_paper_set_parameters_are_valid():
+    # The paper's Set-A/B/C (parameter table): N, L+1, alpha and beta as
+    # printed, every prime 54 bits and 1 mod 2N; digits of alpha primes give
+    # beta = ceil((L+1)/alpha) digits (Set-C: 32 primes, alpha 12, beta 3).
+    table = {"A": (2 ** 13, 5, 5, 1), "B": (2 ** 15, 16, 8, 2), "C": (2 ** 16, 32, 12, 3)}
+    for name, (n, lq, alpha, beta) in table.items():
+        p = W.params_paper_set(name)
+        assert (p.n, p.max_level + 1, p.alpha, p.beta(p.max_level), p.dnum) == (n, lq, alpha, beta, beta)
+        primes = list(p.q) + list(p.p)
+        assert len(set(primes)) == len(primes)
+        for x in primes:
+            assert x.bit_length() == 54 and x % (2 * n) == 1 and W.is_prime(x)
+
+
+def test_paper_set_a_oracle_t3_t4():
+    # T3/T4 at Set-A (N = 2^13, 54-bit primes, one digit): TH-BSGS and plain
+    # BSGS on 32 banded diagonals decrypt to FP64 M v and to each other.
+    prm = W.params_paper_set("A")
+    o = O.Oracle(prm)
+    o.keygen(181)
+    S, delta = prm.slots, 2.0 ** prm.log_delta
+    diags = W.banded_diagonals(182, S, range(32))
+    v = W.input_vector(183, S)
+    level = prm.max_level
+    ct = o.encrypt(level, v, delta, seed=184)
+    keys = o.rotkeys(sorted(set(W.th_rotations(2, 4, 4)) | set(W.bsgs_rotations(4, 8))))
+    th = o.lt_th(level, ct, (2, 4, 4), o.th_plaintexts(diags, 2, 4, 4, delta), keys)
+    bs = o.lt_bsgs(level, ct, (4, 8), o.bsgs_plaintexts(diags, 4, 8, delta), keys)
+    scale = delta * delta / prm.q[level]
+    ref = W.matvec(diags, v)
+    zt, zb = o.decrypt_slots(th, scale), o.decrypt_slots(bs, scale)
+    # The floors of eq. (1) and eq. (4) bias every coefficient of the result
+    # by up to -(alpha + 1)/2 on average.  A constant c in every coefficient
+    # evaluates at zeta^e to c (1 - zeta^(eN)) / (1 - zeta^e), of size about
+    # |c| 2N / (pi e') with e' = min(e, 2N - e): the error lands on the slots
+    # whose 5^t mod 2N is near 0 (slot 0 has e = 1), times |1 + s(zeta^e)|
+    # (~ sqrt(h), taken 8 sqrt(h)) for the c1 part.  At output scale
+    # 2^80 / q_l ~ 2^26, N = 2^13, alpha = 5 that is B / e' with
+    # B = 3 * (2N / pi) * 8 sqrt(192) / 2^26 = 0.026; the rest is rounding
+    # noise (1e-4 covers it).
+    n = prm.n
+    e5 = np.array([pow(5, t, 2 * n) for t in range(S)])
+    bound = 0.026 / np.minimum(e5, 2 * n - e5) + 1e-4
+    for z in (zt, zb):
+        e = np.abs(z - ref)
+        assert np.all(e <= bound)
+        assert np.median(e) <= 3e-5
+    assert np.all(np.abs(zt - zb) <= 2 * bound)
