@@ -453,7 +453,7 @@ def chain_leg(P, prm, steps, torch, H):
 def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
     """Poisson arrivals (seeded) of single-LT requests: N ~ U{2^14, 2^15,
     2^16}, level ~ U{8..24}, n ~ U{32..256} banded; one resident key set per N
-    (split (8,8,4), 17 rotations) and a resident pool of 256 pre-rotated
+    (split (4,16,4), 21 rotations) and a resident pool of 256 pre-rotated
     plaintexts per N at the top level (prefix-truncated by level and n);
     requests admitted by the server within an HBM budget of budget_total bytes
     (resident state included)."""
