@@ -106,9 +106,9 @@ def test_server_two_rings_n15_n16():
 
 
 def test_server_serving_split_n14():
-    # The serving configuration's resident split (8, 8, 4) with up to 256
+    # The serving benchmark's resident split (4, 16, 4) with up to 256
     # diagonals, N = 2^14, requests of different levels and diagonal counts.
-    r14 = Ring(W.params_n16(log_n=14), [(24, 256, (8, 8, 4)), (8, 40, (8, 8, 4)), (15, 200, (8, 8, 4))], 41)
+    r14 = Ring(W.params_n16(log_n=14), [(24, 256, (4, 16, 4)), (8, 40, (4, 16, 4)), (15, 200, (4, 16, 4))], 41)
     order = [(0, 0), (0, 1), (0, 2)]
     log("n14 serving split")
     mix, st = _serve([r14], order, 8 << 30, max_batch=4, max_inflight=2)
