@@ -237,7 +237,7 @@ def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0)
     return wall, ms_events, prof, ws_bytes
 
 
-# The paper's FPGA latency for its dense LTs (its design, Set-A/B/C): context
+# The paper's FPGA latency for its dense LTs (Table VIII, its design, Set-A/B/C): context
 # for the same shapes here, not a like-for-like target.
 PAPER_FPGA_MS = {"A": 19.44, "B": 726.59, "C": 3113.70}
 

@@ -455,6 +455,37 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
 int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int max_keys, const ckks_lt_rates* rates,
                      int* n1, int* n2, int* n3, double* predicted_s);
 
+/*
+ * The paper's off-chip traffic model of its memory-optimized TH-BSGS data
+ * path (Table III, off-chip columns), for its phases 1-6 with the on-chip
+ * parallelism parameters of Table VII: m1, l1 (phase 1), m2, l2 (phase 2:
+ * m2 ModDown results share the Decompose NTT twiddles), m3 keys and m4 digit
+ * sets of l3 limbs on chip (phase 3), m5 (phase 4), m6 (phase 5).  Counts are
+ * in limbs; a ratio of rounds such as (n1'-1)/m2 is rounded up (a phase runs
+ * whole rounds).  n_diag is the LT dimension n of phase 4's matrix reads.
+ * It describes the FPGA design's schedule, not this library's (whose words
+ * ckks_lt_predict prices); it is here to reproduce the paper's traffic
+ * figures (with Table VII's parameters the totals come within 0.3% of
+ * Table VIII's off-chip column for Set-A/B/C).
+ */
+typedef struct {
+  int m1, l1, m2, l2, m3, m4, l3, m5, l4, m6, l5;
+} ckks_th_parallelism;
+
+typedef struct {
+  double phase_limbs[6];  /* off-chip limbs of phases 1..6                     */
+  double twiddle_limbs;   /* per column of Table III, summed over the phases  */
+  double matrix_limbs;
+  double key_limbs;
+  double read_limbs;
+  double write_limbs;
+  double total_limbs;
+  double total_bytes;     /* total_limbs * N * word_bits / 8                   */
+} ckks_th_traffic;
+
+int ckks_th_traffic_model(int log_n, int level, int alpha, int n1, int n2, int n3, int n_diag, int word_bits,
+                          const ckks_th_parallelism* par, ckks_th_traffic* out);
+
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 /* Kernel identifiers: the forward NTT column / row passes, the inverse NTT
  * row / column passes, basis conversion, key-switch inner product (several

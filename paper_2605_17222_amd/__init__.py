@@ -43,7 +43,7 @@ EXPORTED = [
     "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch", "ckks_lt_cost_model", "ckks_lt_autotune",
     "ckks_lt_predict", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit", "ckks_server_poll",
     "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats", "ckks_server_destroy",
-    "ckks_encode_workspace_size", "ckks_encode",
+    "ckks_encode_workspace_size", "ckks_encode", "ckks_th_traffic_model",
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
@@ -99,6 +99,16 @@ class LtRates(ctypes.Structure):
 class LtItem(ctypes.Structure):
     _fields_ = [("in_", Ct), ("diags", Diags), ("keys", ctypes.POINTER(RotKeys)), ("out", Ct),
                 ("status", ctypes.c_int)]
+
+
+class ThParallelism(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int) for f in ("m1", "l1", "m2", "l2", "m3", "m4", "l3", "m5", "l4", "m6", "l5")]
+
+
+class ThTraffic(ctypes.Structure):
+    _fields_ = [("phase_limbs", ctypes.c_double * 6), ("twiddle_limbs", ctypes.c_double),
+                ("matrix_limbs", ctypes.c_double), ("key_limbs", ctypes.c_double), ("read_limbs", ctypes.c_double),
+                ("write_limbs", ctypes.c_double), ("total_limbs", ctypes.c_double), ("total_bytes", ctypes.c_double)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -187,6 +197,8 @@ def lib() -> ctypes.CDLL:
         L.ckks_server_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServerStat)]
         L.ckks_server_destroy.argtypes = [ctypes.c_void_p]
         L.ckks_server_destroy.restype = None
+        L.ckks_th_traffic_model.argtypes = [ctypes.c_int] * 8 + [ctypes.POINTER(ThParallelism),
+                                                                 ctypes.POINTER(ThTraffic)]
         L.ckks_encode_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.ckks_encode.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(EncodeItem), ctypes.c_double,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
@@ -446,6 +458,20 @@ def ckks_lt_cost_model(log_n: int, level: int, alpha: int, algo: int, split: Seq
     _check(lib().ckks_lt_cost_model(log_n, level, alpha, algo, n1, n2, n3, word_bits, ctypes.byref(c)),
            "ckks_lt_cost_model")
     return {f: getattr(c, f) for f, _ in LtCost._fields_}
+
+
+def ckks_th_traffic_model(log_n: int, level: int, alpha: int, split: Sequence[int], n_diag: int, word_bits: int,
+                          par: dict) -> dict:
+    """Off-chip limbs of the paper's memory-optimized data path (Table III) for
+    the parallelism parameters par (keys m1 l1 m2 l2 m3 m4 l3 m5 l4 m6 l5)."""
+    n1, n2, n3 = split
+    p = ThParallelism(*[int(par.get(f, 1)) for f, _ in ThParallelism._fields_])
+    t = ThTraffic()
+    _check(lib().ckks_th_traffic_model(log_n, level, alpha, n1, n2, n3, n_diag, word_bits, ctypes.byref(p),
+                                       ctypes.byref(t)), "ckks_th_traffic_model")
+    out = {f: getattr(t, f) for f, _ in ThTraffic._fields_ if f != "phase_limbs"}
+    out["phase_limbs"] = list(t.phase_limbs)
+    return out
 
 
 def ckks_lt_predict(log_n: int, level: int, alpha: int, algo: int, split: Sequence[int], n_diag: int,

@@ -202,4 +202,35 @@ int ckks_lt_autotune(int log_n, int level, int alpha, int algo, int n_diag, int 
   return CKKS_OK;
 }
 
+int ckks_th_traffic_model(int log_n, int level, int alpha, int n1, int n2, int n3, int n_diag, int word_bits,
+                          const ckks_th_parallelism* par, ckks_th_traffic* out) {
+  if (!par || !out || log_n < 1 || log_n > 30 || level < 0 || alpha < 1 || n1 < 1 || n2 < 1 || n3 < 1 ||
+      n_diag < 0 || word_bits < 1 || par->m2 < 1 || par->m3 < 1 || par->m5 < 1 || par->m6 < 1)
+    return CKKS_E_INVALID_ARG;
+  const double Lq = level + 1.0, K = Lq + alpha, beta = ceil(Lq / alpha), n = n_diag;
+  auto rounds = [](double a, double b) { return ceil(a / b); };
+  const double r2 = rounds(n1 - 1.0, par->m2), r3 = rounds(n2 - 1.0, par->m3);
+  const double r5 = rounds((double)n1 * n2, par->m5), r6 = rounds((double)n3, par->m6);
+  // Table III, one row per phase: (I)NTT twiddles, LT matrix, switching keys,
+  // polynomial reads, polynomial writes
+  const double t[6][5] = {
+      {3 * Lq + 2 * alpha, 0, 2 * (n1 - 1.0) * beta * K, 2 * Lq, 3 * (n1 - 1.0) * K + 2 * Lq},
+      {r2 * K, 0, 0, (n1 - 1.0) * K, (n1 - 1.0) * beta * K},
+      {0, 0, 2 * (n2 - 1.0) * beta * K, r3 * n1 * (beta + 1) * K, 2.0 * n1 * n2 * K},
+      {K, n * K, 0, 2 * (n1 * (double)n2 + (r5 - 1) * n3) * K, 2 * r5 * n3 * K},
+      {r6 * K, 0, 2 * (n3 - 1.0) * beta * K, 2 * (n3 + r6 - 1) * K, 2 * r6 * K},
+      {K, 0, 0, 2 * K, 2 * Lq},
+  };
+  memset(out, 0, sizeof(*out));
+  double* col[5] = {&out->twiddle_limbs, &out->matrix_limbs, &out->key_limbs, &out->read_limbs, &out->write_limbs};
+  for (int p = 0; p < 6; ++p)
+    for (int c = 0; c < 5; ++c) {
+      out->phase_limbs[p] += t[p][c];
+      *col[c] += t[p][c];
+      out->total_limbs += t[p][c];
+    }
+  out->total_bytes = out->total_limbs * ldexp(1.0, log_n) * word_bits / 8.0;
+  return CKKS_OK;
+}
+
 }  // extern "C"

@@ -98,3 +98,31 @@ def test_predictor_structure():
     # lower levels are cheaper; custom rates are honoured (zero rates: zero time)
     assert H.ckks_lt_predict(16, 8, 9, H.CKKS_LT_TH_BSGS, (4, 4, 4), 64) < ts[-1]
     assert H.ckks_lt_predict(16, 24, 9, H.CKKS_LT_BSGS, (8, 8), 64, rates=(0.0, 0.0, 1e300, 0.0)) < 1e-200
+
+
+def test_traffic_model_reproduces_paper_offchip():
+    # Table III's off-chip columns with Table VII's parallelism give the
+    # off-chip access of Table VIII for Set-A/B/C (the table's GB are 2^30
+    # bytes of w = 54-bit words) within 0.3%.
+    t = GOLDEN["table8_offchip"]
+    for name, s in t["sets"].items():
+        r = H.ckks_th_traffic_model(s["log_n"], s["L1"] - 1, s["alpha"], s["split"], s["n"], t["w"], s["par"])
+        gib = r["total_bytes"] / 2 ** 30
+        assert abs(gib / s["offchip_gb"] - 1) < 3e-3, (name, gib)
+        assert abs(sum(r["phase_limbs"]) - r["total_limbs"]) < 1e-6 * r["total_limbs"]
+        # the LT matrix dominates (phase 4 reads n (L+1+alpha) limbs)
+        assert r["matrix_limbs"] == s["n"] * (s["L1"] + s["alpha"])
+
+
+def test_traffic_model_structure():
+    # Phase 1 without inner rotations reads only the ciphertext and the
+    # twiddles; doubling m5 halves phase 4's write rounds; bad input is refused.
+    par = dict(m1=1, l1=1, m2=1, l2=1, m3=1, m4=1, l3=1, m5=1, l4=1, m6=1, l5=1)
+    r = H.ckks_th_traffic_model(16, 31, 12, (1, 32, 32), 1024, 54, par)
+    K = 44
+    assert r["phase_limbs"][0] == 3 * 32 + 24 + 2 * 32 + 2 * 32
+    a = H.ckks_th_traffic_model(16, 31, 12, (4, 8, 32), 1024, 54, dict(par, m5=4))
+    b = H.ckks_th_traffic_model(16, 31, 12, (4, 8, 32), 1024, 54, dict(par, m5=8))
+    assert a["write_limbs"] - b["write_limbs"] == 2 * (8 - 4) * 32 * K
+    with pytest.raises(H.CkksError):
+        H.ckks_th_traffic_model(16, 31, 12, (4, 8, 32), 1024, 54, dict(par, m2=0))

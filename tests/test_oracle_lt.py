@@ -147,7 +147,7 @@ def test_dh_counts_table1(toy, split):
 
 
 def test_paper_set_parameters_are_valid():
-    # The paper's Set-A/B/C (parameter table): N, L+1, alpha and beta as
+    # The paper's Set-A/B/C (Table V): N, L+1, alpha and beta as
     # printed, every prime 54 bits and 1 mod 2N; digits of alpha primes give
     # beta = ceil((L+1)/alpha) digits (Set-C: 32 primes, alpha 12, beta 3).
     table = {"A": (2 ** 13, 5, 5, 1), "B": (2 ** 15, 16, 8, 2), "C": (2 ** 16, 32, 12, 3)}

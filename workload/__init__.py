@@ -128,7 +128,7 @@ def params_n16(log_n: int = 16) -> Params:
 
 
 # The paper's evaluation sets (N, L+1, alpha, beta; w = 54-bit words) with the
-# dense LT dimension n = N/2 and the TH-BSGS split of its parameter table.
+# dense LT dimension n = N/2 (Table V) and the TH-BSGS split of Table VII.
 PAPER_SETS = {
     "A": dict(log_n=13, n_q=5, alpha=5, dnum=1, split=(16, 16, 16)),
     "B": dict(log_n=15, n_q=16, alpha=8, dnum=2, split=(32, 16, 32)),
