@@ -304,22 +304,48 @@ def cpu_baseline(prm, level, split):
                       "keygen/encoding excluded; decrypted max err %.1e" % (reps, err)}
 
 
-def batched_leg(P, prm, items, steps, torch, H, seed=77, chunk=32):
-    """Ragged batch: `items` ciphertexts, level ~ U{8..24}, diagonal count ~
-    U{16, 32, 64, 128} (banded), each with its own plaintexts and an
-    autotuned TH split; keys shared.  A step evaluates every item, `chunk`
-    items per ckks_lt_eval_batch call (the calls share one workspace)."""
+def ragged_specs(prm, items, H, seed=77):
+    """(level, n_diag, autotuned split) of each item of the ragged batch:
+    level ~ U{8..24}, n_diag ~ U{16, 32, 64, 128} (seeded)."""
     import numpy as np
-    import workload as W
     rng = np.random.Generator(np.random.PCG64([seed, 5]))
-    residues = residue_maker(prm.n, torch, seed)
-    pq = list(prm.p) + list(prm.q)
     specs = []
     for _ in range(items):
         level = int(rng.integers(8, 25))
         nd = int(rng.choice([16, 32, 64, 128]))
         sp, _ = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, nd)
         specs.append((level, nd, tuple(sp)))
+    return specs
+
+
+def serving_requests(seconds, rate, seed=2024):
+    """The serving stream: (arrival s, ring 0..2 for N = 2^14..2^16, level ~
+    U{8..24}, n_diag ~ U{32..256}, ciphertext 0..3) per request (seeded)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64([seed, 6]))
+    nreq = int(seconds * rate)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    reqs = []
+    for i in range(nreq):
+        g = int(rng.integers(0, 3))
+        level = int(rng.integers(8, 25))
+        nd = int(rng.integers(32, 257))
+        reqs.append((float(arrivals[i]), g, level, nd, int(rng.integers(0, 4))))
+    return reqs
+
+
+SERVING_SPLIT = (4, 16, 4)
+
+
+def batched_leg(P, prm, items, steps, torch, H, seed=77, chunk=32):
+    """Ragged batch: `items` ciphertexts, level ~ U{8..24}, diagonal count ~
+    U{16, 32, 64, 128} (banded), each with its own plaintexts and an
+    autotuned TH split; keys shared.  A step evaluates every item, `chunk`
+    items per ckks_lt_eval_batch call (the calls share one workspace)."""
+    import workload as W
+    residues = residue_maker(prm.n, torch, seed)
+    pq = list(prm.p) + list(prm.q)
+    specs = ragged_specs(prm, items, H, seed)
     rots = sorted(set().union(*[W.th_rotations(*sp) for _, _, sp in specs]))
     keys = device_keys(prm, rots, residues)
     delta = 2.0 ** prm.log_delta
@@ -450,16 +476,16 @@ def chain_leg(P, prm, steps, torch, H):
             "compulsory_bytes_per_chain": comp, "effective_GB_per_s": round(comp * steps / wall / 1e9, 1)}
 
 
-def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
+def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024, onfly=False):
     """Poisson arrivals (seeded) of single-LT requests: N ~ U{2^14, 2^15,
     2^16}, level ~ U{8..24}, n ~ U{32..256} banded; one resident key set per N
     (split (4,16,4), 21 rotations) and a resident pool of 256 pre-rotated
-    plaintexts per N at the top level (prefix-truncated by level and n);
-    requests admitted by the server within an HBM budget of budget_total bytes
-    (resident state included)."""
-    import numpy as np
+    plaintexts per N at the top level (prefix-truncated by level and n) --
+    or, with onfly, a pool of 256 slot vectors per N that the library encodes
+    for each request; requests admitted by the server within an HBM budget of
+    budget_total bytes (resident state included)."""
     import workload as W
-    split = (4, 16, 4)
+    split = SERVING_SPLIT
     rings, resident = [], 0
     for log_n in (14, 15, 16):
         prm = W.params_n16(log_n=log_n)
@@ -468,22 +494,23 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
         pq = list(prm.p) + list(prm.q)
         kmax = prm.alpha + prm.max_level + 1
         keys = device_keys(prm, W.th_rotations(*split), residues)
-        pool = [residues(pq[:kmax]) for _ in range(256)]
+        if onfly:
+            z = torch.empty((256, prm.slots), dtype=torch.complex128, device="cuda")
+            torch.view_as_real(z).uniform_(-1.0, 1.0)
+            pool = [z[t] for t in range(256)]
+            pool_bytes = z.numel() * 16
+        else:
+            pool = [residues(pq[:kmax]) for _ in range(256)]
+            pool_bytes = 256 * kmax * prm.n * 8
         cts = [(residues(list(prm.q)), residues(list(prm.q))) for _ in range(4)]
-        resident += sum(k.numel() * 8 for k in keys.values()) + 256 * kmax * prm.n * 8 + 4 * 2 * 25 * prm.n * 8
+        resident += sum(k.numel() * 8 for k in keys.values()) + pool_bytes + 4 * 2 * 25 * prm.n * 8
         rings.append((prm, P, keys, pool, cts))
-    rng = np.random.Generator(np.random.PCG64([seed, 6]))
     nreq = int(seconds * rate)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
     reqs = []
     out_bytes = 0
-    for i in range(nreq):
-        g = int(rng.integers(0, 3))
-        level = int(rng.integers(8, 25))
-        nd = int(rng.integers(32, 257))
+    for at, g, level, nd, ci in serving_requests(seconds, rate, seed):
         prm = rings[g][0]
-        reqs.append((float(arrivals[i]), g, level, nd, int(rng.integers(0, 4)),
-                     (H.empty((level, prm.n)), H.empty((level, prm.n)))))
+        reqs.append((at, g, level, nd, ci, (H.empty((level, prm.n)), H.empty((level, prm.n)))))
         out_bytes += 2 * level * prm.n * 8
     resident += out_bytes
     free, _ = torch.cuda.mem_get_info()
@@ -502,7 +529,7 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
                 prm, P, keys, pool, cts = rings[g]
                 c0, c1 = cts[ci]
                 H.ckks_server_submit(S, rid[g], level, 2.0 ** prm.log_delta, c0, c1, split, pool[:nd],
-                                     2.0 ** prm.log_delta, o0, o1)
+                                     2.0 ** prm.log_delta, o0, o1, onfly=onfly)
             H.ckks_server_wait_all(S)
             wall = time.perf_counter() - t0
             st = H.ckks_server_stats(S)
@@ -518,7 +545,9 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024):
            "burst": {"requests": min(nreq, 400), "lt_per_s": round(stb["completed"] / max(stb["span_s"], 1e-9), 1),
                      "p50_ms": round(stb["p50_s"] * 1e3, 2), "p99_ms": round(stb["p99_s"] * 1e3, 2)},
            "recipe": "Poisson %.0f req/s, N ~ U{2^14,2^15,2^16}, level ~ U{8..24}, n ~ U{32..256}, split (4,16,4), "
-                     "seed %d; max_batch 8, 2 streams" % (rate, seed)}
+                     "seed %d; max_batch 8, 2 streams; %s" % (rate, seed, "diagonals as resident slot vectors, "
+                                                              "encoded on the fly" if onfly else
+                                                              "resident plaintext pool")}
     del rings, reqs
     torch.cuda.empty_cache()
     return res
@@ -642,6 +671,8 @@ def main():
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(args.serve_seconds, args.serve_rate, torch, H)
         print("serving leg done", flush=True, file=sys.stderr)
+        out["serving_onfly"] = serving_leg(args.serve_seconds, args.serve_rate, torch, H, onfly=True)
+        print("on-the-fly serving leg done", flush=True, file=sys.stderr)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prm, level, th_split)
     print(json.dumps(out), flush=True)
