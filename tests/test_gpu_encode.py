@@ -334,3 +334,34 @@ def test_onfly_mixed_ragged_batch_and_graph():
         torch.cuda.synchronize()
         for e, x in zip(eager, outputs()):
             assert np.array_equal(e, x), rep
+
+
+def test_onfly_random_configurations():
+    # Seeded random TH-/DH-BSGS configurations with slot diagonals: split,
+    # level, a sparse random subset of the diagonals, stride and centre.
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(191)
+    S = prm.slots
+    rng = np.random.Generator(np.random.PCG64(192))
+    cases = []
+    for c in range(12):
+        algo = "th" if c % 3 else "dh"
+        split = tuple(int(x) for x in rng.choice([1, 2, 4], size=3 if algo == "th" else 2))
+        n = int(np.prod(split))
+        stride = int(rng.choice([1, 1, 3, 5, 16]))
+        centre = int(rng.integers(0, n))
+        level = int(rng.integers(1, prm.max_level + 1))
+        present = sorted(set(int(t) for t in rng.choice(n, size=int(rng.integers(1, n + 1)))))
+        cases.append((algo, split, stride, centre, level, present))
+    rots = set()
+    for algo, split, stride, centre, _, _ in cases:
+        th_split = split if algo == "th" else (1,) + split
+        rots |= set(W.th_rotations(*th_split, stride=stride, centre=centre, slots=S))
+    keys = o.rotkeys(sorted(rots))
+    for c, (algo, split, stride, centre, level, present) in enumerate(cases):
+        offs = {t: (stride * (t - centre)) % S for t in present}
+        dg = W.banded_diagonals(200 + c, S, sorted(offs.values()))
+        log("case", c, algo, split, "stride", stride, "centre", centre, "level", level, "present", len(present))
+        _onfly_case(prm, o, keys, level, split, {t: dg[offs[t]] for t in present}, W.input_vector(220 + c, S),
+                    240 + c, algo=algo, stride=stride, centre=centre)
