@@ -3,7 +3,12 @@
  * plaintext-matrix x encrypted-vector linear transformations (HE-LT) in
  * RNS-CKKS, by the triple-hoisted baby-step giant-step algorithm
  * (Akherati & Zhang, arXiv 2605.17222, Algorithm 2 and eq. (6)) and by the
- * plain BSGS algorithm it is compared with (eq. (5), Table I).
+ * plain BSGS algorithm it is compared with (eq. (5), Table I), the
+ * double-hoisted BSGS (Algorithm 1) and the diagonal method.  Around it:
+ * ragged batches in lockstep, a continuous-batching server, plaintext
+ * encoding on the device (also on the fly inside an LT, for dense matrices),
+ * one call per step of the path, the operation-count model with a split
+ * autotuner, the paper's off-chip traffic model, and kernel timing.
  *
  * Every call takes plain pointers and sizes.  Pointers documented as "device"
  * point to GPU memory on the device that was current when the parameter set
