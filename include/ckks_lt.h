@@ -120,11 +120,12 @@ typedef struct {
  * progression must not repeat an offset: n1 n2 n3 (or n_diag) indices at
  * most N/2 / gcd(s, N/2).
  *
- * On-the-fly plaintexts (TH-BSGS and DH-BSGS only): with pt = NULL and
- * slots set, slots[t] is the diagonal itself as N/2 complex slot values
- * (device [N/2][2] doubles, re and im; NULL = absent) and the library encodes
- * f^_t = encode(rot(diag_t, -G_k)) with scale pt_scale at the ciphertext's
- * level (as ckks_encode does) right before the multiply-accumulate that
+ * On-the-fly plaintexts: with pt = NULL and slots set, slots[t] is the
+ * diagonal itself as N/2 complex slot values (device [N/2][2] doubles, re and
+ * im; NULL = absent) and the library encodes the plaintext above
+ * (f^_t = encode(rot(diag_t, -G)) for TH-, DH- and plain BSGS, encode(diag_t)
+ * for the diagonal method) with scale pt_scale at the ciphertext's level and
+ * basis (as ckks_encode does) right before the multiply-accumulate that
  * consumes it, so no plaintext outlives its use: a dense n = N/2 matrix
  * needs N/2 slot vectors (16 B per slot) instead of n resident plaintexts of
  * alpha + l + 1 limbs.  The workspace then also holds the plaintexts of one

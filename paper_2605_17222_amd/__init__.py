@@ -311,7 +311,7 @@ def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequen
                  pt_scale: float, keys: Optional[Dict[int, object]], algo: int, out0, out1, ws, ws_bytes: int,
                  stream=None, stride: int = 1, centre: int = 0, onfly: bool = False) -> Tuple[int, float]:
     """Enqueue out = LT(in); returns (out level, out scale).  onfly: pts are
-    slot vectors encoded by the library with pt_scale (TH-/DH-BSGS)."""
+    slot vectors encoded by the library with pt_scale."""
     cin = Ct(level, scale, _ptr(c0), _ptr(c1))
     cout = Ct(level - 1, 0.0, _ptr(out0), _ptr(out1))
     d, keep1 = _diags(split, pts, pt_scale, stride, centre, onfly)

@@ -741,12 +741,20 @@ void lt_bsgs(Run& R, int level, const uint64_t* c0, const uint64_t* c1, int n1, 
       }
     for (int i = 0; i < n1; ++i) {
       if (!used_i[i]) continue;
-      MacTerm t{R0[i], R1[i], false, {}};
-      for (int j : js) t.f.push_back(j >= 0 && D.has(n1 * j + i) ? D.pt[n1 * j + i] : nullptr);
+      MacTerm t{R0[i], R1[i], false, {}, {}};
+      for (int j : js) {
+        const bool h = j >= 0 && D.has(n1 * j + i);
+        if (D.z) t.z.push_back(h ? D.z[n1 * j + i] : nullptr);
+        t.f.push_back(h && !D.z ? D.pt[n1 * j + i] : nullptr);
+      }
       terms.push_back(t);
     }
-    if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, std::vector<const uint64_t*>(js.size(), nullptr)});
-    ptmac(R, Lq, P->alpha, terms, out0, out1);
+    if (terms.empty())
+      terms.push_back(MacTerm{c0, c1, false, std::vector<const uint64_t*>(js.size(), nullptr), {}});
+    MacEnc enc;  // on-the-fly plaintexts: f^ = encode(rot(diag, -G_j)) at the Q basis
+    enc.scale = D.zscale;
+    for (int j : js) enc.rot.push_back(j >= 0 ? -giant(j) : 0);
+    ptmac(R, Lq, P->alpha, terms, out0, out1, D.z ? &enc : nullptr);
   }
   // Giant steps: A += Rot(S_j, G_j).
   {
@@ -785,11 +793,18 @@ void lt_naive(Run& R, int level, const uint64_t* c0, const uint64_t* c1, long st
   for (size_t u = 0; u < ts.size(); ++u)
     jobs.push_back(RotJob{c0, c1, stride * (ts[u] - centre), T0[u], T1[u], false});
   rotate(R, level, jobs, ks);
+  // on-the-fly plaintexts: f_t = encode(diag_t) at the Q basis (no pre-rotation)
+  auto term = [&](const uint64_t* a, const uint64_t* b, int t) {
+    return D.z ? MacTerm{a, b, false, {nullptr}, {D.z[t]}} : MacTerm{a, b, false, {D.pt[t]}, {}};
+  };
   std::vector<MacTerm> terms;
-  if (tdir >= 0) terms.push_back(MacTerm{c0, c1, false, {D.pt[tdir]}});
-  for (size_t u = 0; u < ts.size(); ++u) terms.push_back(MacTerm{T0[u], T1[u], false, {D.pt[ts[u]]}});
-  if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, {nullptr}});
-  ptmac(R, Lq, P->alpha, terms, {A0}, {A1});
+  if (tdir >= 0) terms.push_back(term(c0, c1, tdir));
+  for (size_t u = 0; u < ts.size(); ++u) terms.push_back(term(T0[u], T1[u], ts[u]));
+  if (terms.empty()) terms.push_back(MacTerm{c0, c1, false, {nullptr}, {}});
+  MacEnc enc;
+  enc.scale = D.zscale;
+  enc.rot.push_back(0);
+  ptmac(R, Lq, P->alpha, terms, {A0}, {A1}, D.z ? &enc : nullptr);
   divide(R, DIV_RESCALE, Jobs{{level, A0, o0}, {level, A1, o1}});
 }
 
@@ -810,10 +825,7 @@ int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* dia
   if (level < 1 || level > P->L) return CKKS_E_INVALID_ARG;
   if (diags->n_diag < 0 || (diags->n_diag > 0 && !diags->pt && !diags->slots) || (diags->pt && diags->slots))
     return CKKS_E_INVALID_ARG;
-  if (diags->slots) {
-    if (algo != CKKS_LT_TH_BSGS && algo != CKKS_LT_DH_BSGS) return CKKS_E_UNSUPPORTED;
-    if (!(diags->pt_scale > 0) || !std::isfinite(diags->pt_scale)) return CKKS_E_INVALID_ARG;
-  }
+  if (diags->slots && (!(diags->pt_scale > 0) || !std::isfinite(diags->pt_scale))) return CKKS_E_INVALID_ARG;
   if (check_buffers) {
     if (!in->c0 || !in->c1 || !out->c0 || !out->c1) return CKKS_E_INVALID_ARG;
     const size_t N = (size_t)P->n;
@@ -895,6 +907,8 @@ void run_items(Run& R, int algo, const std::vector<const ckks_ct*>& in, const st
     Diag D;
     D.n = dg[t]->n_diag;
     D.pt = dg[t]->pt;
+    D.z = dg[t]->slots;
+    D.zscale = dg[t]->pt_scale;
     const long stride = prog_stride(dg[t]), centre = dg[t]->centre;
     if (algo == CKKS_LT_BSGS)
       lt_bsgs(R, in[t]->level, in[t]->c0, in[t]->c1, dg[t]->n1, dg[t]->n2, stride, centre, D, ks[t], out[t]->c0,

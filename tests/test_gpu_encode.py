@@ -87,43 +87,65 @@ def test_encode_n16_against_oracle():
     _encode_case(prm, 3, 52, [(0, K)])
 
 
-def _th_pre_rotations(split, n, stride, centre, S):
-    n1, n2, _ = split
-    return [-(stride * (n1 * n2 * (t // (n1 * n2)) - centre)) % S for t in range(n)]
+def _pre_rotations(algo, split, n, stride, centre, S):
+    """The giant-step rotation folded into plaintext t (0 for the diagonal method)."""
+    if algo == "naive":
+        return [0] * n
+    block = split[0] * split[1] if algo == "th" else split[0]
+    return [-(stride * (block * (t // block) - centre)) % S for t in range(n)]
 
 
-def _onfly_case(prm, o, keys, level, split, diags_by_t, v, seed, algo="th", stride=1, centre=0, tol=5e-3):
+def _onfly_case(prm, o, keys, level, split, diags_by_t, v, seed, algo="th", stride=1, centre=0, tol=5e-3, n=None):
     """Runs the LT with slot diagonals encoded on the fly and with the device's
     own encodings as plaintexts; both must equal the oracle's LT given those
-    encodings, and decrypt to M v."""
+    encodings, and decrypt to M v.  algo: th, dh, bsgs or naive (n indices)."""
     import torch
     P = gpu_params(prm)
     S, delta = prm.slots, 2.0 ** prm.log_delta
-    th_split = split if algo == "th" else (1,) + tuple(split)
-    n = int(np.prod(th_split))
+    if algo in ("th", "dh"):
+        osplit = tuple(split) if algo == "th" else (1,) + tuple(split)
+        n = int(np.prod(osplit))
+        first, nl = 0, prm.alpha + prm.max_level + 1
+        rots = W.th_rotations(*osplit, stride=stride, centre=centre, slots=S)
+        pre = _pre_rotations("th", osplit, n, stride, centre, S)
+    elif algo == "bsgs":
+        osplit = tuple(split)
+        n = int(np.prod(osplit))
+        first, nl = prm.alpha, prm.max_level + 1
+        rots = W.bsgs_rotations(*osplit, stride=stride, centre=centre, slots=S)
+        pre = _pre_rotations("bsgs", osplit, n, stride, centre, S)
+    else:
+        osplit = None
+        first, nl = prm.alpha, prm.max_level + 1
+        rots = sorted(set((stride * (t - centre)) % S for t in range(n) if diags_by_t.get(t) is not None) - {0})
+        pre = _pre_rotations("naive", None, n, stride, centre, S)
     ts = [t for t in range(n) if diags_by_t.get(t) is not None]
-    pre = _th_pre_rotations(th_split, n, stride, centre, S)
-    K = prm.alpha + prm.max_level + 1
-    enc, _ = _encode(P, prm, [diags_by_t[t] for t in ts], [pre[t] for t in ts], delta, 0, K)
+    enc, _ = _encode(P, prm, [diags_by_t[t] for t in ts], [pre[t] for t in ts], delta, first, nl)
     pts = [None] * n
     for t, f in zip(ts, enc):
         pts[t] = f
     ct = o.encrypt(level, v, delta, seed=seed)
-    th_keys = {r: keys[r] for r in W.th_rotations(*th_split, stride=stride, centre=centre, slots=S)}
-    log("oracle LT", prm.log_n, "level", level, "split", th_split, "diagonals", len(ts))
-    ref = o.lt_th(level, ct, th_split, pts, th_keys, stride=stride, centre=centre)
-    code = H.CKKS_LT_TH_BSGS if algo == "th" else H.CKKS_LT_DH_BSGS
-    dkeys = {r: limbs_tensor(k) for r, k in th_keys.items()}
+    okeys = {r: keys[r] for r in rots}
+    log("oracle LT", prm.log_n, algo, "level", level, "split", osplit, "diagonals", len(ts))
+    if algo in ("th", "dh"):
+        ref = o.lt_th(level, ct, osplit, pts, okeys, stride=stride, centre=centre)
+    elif algo == "bsgs":
+        ref = o.lt_bsgs(level, ct, osplit, pts, okeys, stride=stride, centre=centre)
+    else:
+        ref = o.lt_naive(level, ct, pts, okeys, stride=stride, centre=centre)
+    code = {"th": H.CKKS_LT_TH_BSGS, "dh": H.CKKS_LT_DH_BSGS, "bsgs": H.CKKS_LT_BSGS, "naive": H.CKKS_LT_NAIVE}[algo]
+    gsplit = split if algo != "naive" else (1, 1, 1)
+    dkeys = {r: limbs_tensor(k) for r, k in okeys.items()}
     c0, c1 = limbs_tensor(ct[0]), limbs_tensor(ct[1])
     dslots = [None if diags_by_t.get(t) is None else _slots_tensor(diags_by_t[t]) for t in range(n)]
     dpts = [None if f is None else limbs_tensor(f) for f in pts]
     res = []
     for onfly, items in ((True, dslots), (False, dpts)):
-        wsb = H.ckks_lt_workspace_size(P, level, split, items, code, stride=stride, centre=centre, onfly=onfly)
+        wsb = H.ckks_lt_workspace_size(P, level, gsplit, items, code, stride=stride, centre=centre, onfly=onfly)
         ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
         o0, o1 = H.empty((level, prm.n)), H.empty((level, prm.n))
         log("device LT onfly" if onfly else "device LT plaintexts", "workspace", wsb)
-        lvl, sc = H.ckks_lt_eval(P, level, delta, c0, c1, split, items, delta, dkeys, code, o0, o1, ws, wsb,
+        lvl, sc = H.ckks_lt_eval(P, level, delta, c0, c1, gsplit, items, delta, dkeys, code, o0, o1, ws, wsb,
                                  stride=stride, centre=centre, onfly=onfly)
         torch.cuda.synchronize()
         res.append((np.stack([H.to_host(o0), H.to_host(o1)]), sc))
@@ -255,11 +277,7 @@ def test_encode_and_onfly_argument_errors():
     with pytest.raises(H.CkksError) as e:
         H.ckks_encode(P, [z], [0], delta, 0, K, [out], ws, 0)
     assert e.value.code == H.CKKS_E_WORKSPACE
-    # slot diagonals: TH-/DH-BSGS only; pt and slots together are refused
-    for algo, code in ((H.CKKS_LT_BSGS, H.CKKS_E_UNSUPPORTED), (H.CKKS_LT_NAIVE, H.CKKS_E_UNSUPPORTED)):
-        with pytest.raises(H.CkksError) as e:
-            H.ckks_lt_workspace_size(P, 1, (2, 2), [z] * 4, algo, onfly=True)
-        assert e.value.code == code
+    # pt and slots together are refused
     d, keep = H._diags((2, 2, 1), [z] * 4, delta, onfly=True)
     d.pt = d.slots
     import ctypes
@@ -293,7 +311,7 @@ def test_onfly_mixed_ragged_batch_and_graph():
         v = W.input_vector(160 + i, S)
         ct = o.encrypt(level, v, delta, seed=170 + i)
         n = int(np.prod(split))
-        pre = _th_pre_rotations(split, n, 1, 0, S)
+        pre = _pre_rotations("th", split, n, 1, 0, S)
         enc, _ = _encode(P, prm, [diags[t] for t in range(nd)], [pre[t] for t in range(nd)], delta, 0, K)
         pts = enc + [None] * (n - nd)
         refs.append(o.lt_th(level, ct, split, pts, keys))
@@ -365,3 +383,27 @@ def test_onfly_random_configurations():
         log("case", c, algo, split, "stride", stride, "centre", centre, "level", level, "present", len(present))
         _onfly_case(prm, o, keys, level, split, {t: dg[offs[t]] for t in present}, W.input_vector(220 + c, S),
                     240 + c, algo=algo, stride=stride, centre=centre)
+
+
+def test_onfly_bsgs_and_diagonal_method():
+    # Plain BSGS (Q-basis plaintexts pre-rotated by -G_j) and the diagonal
+    # method (no pre-rotation) with slot diagonals, banded and strided.
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(251)
+    S = prm.slots
+    cases = [("bsgs", (4, 4), 1, 0, 16), ("bsgs", (8, 4), 3, 5, 20), ("naive", None, 1, 0, 12),
+             ("naive", None, 5, 3, 9)]
+    rots = set()
+    for algo, split, stride, centre, nd in cases:
+        if algo == "bsgs":
+            rots |= set(W.bsgs_rotations(*split, stride=stride, centre=centre, slots=S))
+        else:
+            rots |= set((stride * (t - centre)) % S for t in range(nd)) - {0}
+    keys = o.rotkeys(sorted(rots))
+    for c, (algo, split, stride, centre, nd) in enumerate(cases):
+        offs = {t: (stride * (t - centre)) % S for t in range(nd)}
+        dg = W.banded_diagonals(260 + c, S, sorted(offs.values()))
+        log("case", c, algo, split, "stride", stride, "centre", centre, "diagonals", nd)
+        _onfly_case(prm, o, keys, 1 + c % prm.max_level, split, {t: dg[offs[t]] for t in range(nd)},
+                    W.input_vector(270 + c, S), 280 + c, algo=algo, stride=stride, centre=centre, n=nd)
