@@ -151,13 +151,13 @@ def step_percentiles(P, prm, level, split, reps, torch, H):
 SHOUP_PEAK_T_PER_S = 1.2
 
 
-def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99):
-    """TH-BSGS LT whose diagonals (offsets 0 .. n_diag-1, complex uniform
-    [-1, 1] slot vectors resident on the device) the library encodes right
-    before each multiply-accumulate; keys and ciphertext uniform residues.
-    One extra step with every kernel timed gives the breakdown."""
+def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99, algo="th"):
+    """TH-BSGS (or plain BSGS) LT whose diagonals (offsets 0 .. n_diag-1,
+    complex uniform [-1, 1] slot vectors resident on the device) the library
+    encodes right before each multiply-accumulate; keys and ciphertext uniform
+    residues.  One extra step with every kernel timed gives the breakdown."""
     S, n = prm.slots, prm.n
-    c0, c1, keys, _ = make_inputs(P, prm, level, split, "th", 4321, torch, H, with_pts=False)
+    c0, c1, keys, _ = make_inputs(P, prm, level, split, algo, 4321, torch, H, with_pts=False)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     z = torch.empty((n_diag, S), dtype=torch.complex128, device="cuda")
@@ -165,7 +165,7 @@ def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99):
     for t0 in range(0, n_diag, 1024):
         zr[t0:t0 + 1024].uniform_(-1.0, 1.0, generator=g)
     slots = [z[t] for t in range(n_diag)]
-    code = H.CKKS_LT_TH_BSGS
+    code = H.CKKS_LT_TH_BSGS if algo == "th" else H.CKKS_LT_BSGS
     ws_bytes = H.ckks_lt_workspace_size(P, level, split, slots, code, onfly=True)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     out0, out1 = H.empty((level, n)), H.empty((level, n))
@@ -185,11 +185,11 @@ def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99):
     torch.cuda.synchronize()
     prof = {name: H.ckks_profile_read(k) for k, name in enumerate(H.KERNELS)}
     H.ckks_profile_enable(0)
-    K = prm.alpha + level + 1
+    K = prm.alpha + level + 1 if algo == "th" else level + 1  # plaintext limbs
     beta_max = -(-(prm.max_level + 1) // prm.alpha)
     kmax = prm.alpha + prm.max_level + 1
     key_bytes = len(keys) * beta_max * 2 * kmax * n * 8
-    res = {"split": list(split), "n_diag": n_diag, "level": level, "keys": len(keys),
+    res = {"algo": algo, "split": list(split), "n_diag": n_diag, "level": level, "keys": len(keys),
            "ms_per_lt": round(ms / steps, 3), "lt_per_s": round(steps / wall, 3),
            "plaintexts_encoded_per_s": round(n_diag * steps / wall, 1),
            "slot_bytes": z.numel() * 16, "key_bytes": key_bytes,
@@ -255,6 +255,12 @@ def paper_sets_leg(steps, torch, H):
         r["N"] = prm.n
         r["alpha"] = prm.alpha
         r["paper_fpga_ms"] = PAPER_FPGA_MS[name]
+        # plain BSGS on the same dense matrix (Q-basis plaintexts, one
+        # Decompose per rotation), baby/giant steps as in Table II
+        half = (prm.slots.bit_length() - 1) // 2
+        bs = (1 << (prm.slots.bit_length() - 1 - half), 1 << half)
+        b = onfly_leg(P, prm, prm.max_level, bs, prm.slots, steps, 1, torch, H, algo="bsgs")
+        r["plain_bsgs"] = {k: b[k] for k in ("split", "keys", "ms_per_lt", "key_bytes", "kernels_ms_per_lt")}
         res["set_" + name] = r
         del P
         print("set %s done" % name, flush=True, file=sys.stderr)
