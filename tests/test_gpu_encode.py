@@ -407,3 +407,13 @@ def test_onfly_bsgs_and_diagonal_method():
         log("case", c, algo, split, "stride", stride, "centre", centre, "diagonals", nd)
         _onfly_case(prm, o, keys, 1 + c % prm.max_level, split, {t: dg[offs[t]] for t in range(nd)},
                     W.input_vector(270 + c, S), 280 + c, algo=algo, stride=stride, centre=centre, n=nd)
+
+
+@pytest.mark.parametrize("which", ["set_a_n13", "n14", "n15"])
+def test_encode_every_ring_size(which):
+    # The FFT's two-pass split differs per ring size (A x B = N/2): N = 2^13,
+    # 2^14 and 2^15 here, 2^12 and 2^16 above.
+    prm = {"set_a_n13": lambda: W.params_paper_set("A"), "n14": lambda: W.params_n16(log_n=14),
+           "n15": lambda: W.params_n16(log_n=15)}[which]()
+    K = prm.alpha + prm.max_level + 1
+    _encode_case(prm, 4, 53, [(0, K)])
