@@ -89,8 +89,9 @@ def events_ms(torch, stream, fn, reps):
     return e0.elapsed_time(e1), time.perf_counter() - t0
 
 
-def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True):
-    """Uniform residues on the device for the ciphertext, keys and plaintexts."""
+def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True, packed=False):
+    """Uniform residues on the device for the ciphertext, keys and plaintexts
+    (packed: keys and TH-BSGS plaintexts in the packed resident layout)."""
     import workload as W
     n = prm.n
     pq = list(prm.p) + list(prm.q)
@@ -118,6 +119,11 @@ def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True):
     for r in rots:
         keys[r] = residues(pq[:kmax] * (2 * beta_max)).view(beta_max, 2, kmax, n)
     pts = [residues(pt_mods) for _ in range(n_pt)] if with_pts else []
+    if packed:
+        keys = {r: H.ckks_pack(P, k) for r, k in keys.items()}
+        if algo == "th":
+            pts = [H.ckks_pack(P, f) for f in pts]
+        torch.cuda.synchronize()
     return c0, c1, keys, pts
 
 
@@ -201,8 +207,8 @@ def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99, al
     return res
 
 
-def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0):
-    c0, c1, keys, pts = make_inputs(P, prm, level, split, algo, 1234, torch, H)
+def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0, packed=False):
+    c0, c1, keys, pts = make_inputs(P, prm, level, split, algo, 1234, torch, H, packed=packed)
     code = H.CKKS_LT_TH_BSGS if algo == "th" else H.CKKS_LT_BSGS
     ws_bytes = H.ckks_lt_workspace_size(P, level, split, pts, code)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
@@ -653,6 +659,17 @@ def main():
     out["autotuned_split"] = {"split": list(at_split), "predicted_ms": round(at_pred * 1e3, 4),
                               "ms_per_lt": round(ms_a / args.steps, 4), "lt_per_s": round(args.steps / wall_a, 2),
                               "compulsory_bytes_per_lt": compulsory_bytes(prm, level, at_split, "th")}
+    # the same LTs with keys and TH-BSGS plaintexts resident in the packed
+    # layout (limbs of the 40-bit primes in 5 bytes per coefficient): bit-
+    # identical results, fewer bytes for the key-switch and MAC kernels
+    packed = {}
+    for name, split, algo in (("th", th_split, "th"), ("th_autotuned", at_split, "th"), ("plain_bsgs", bs_split, "bsgs")):
+        wall_p, ms_p, _, _ = time_lt(P, prm, level, split, algo, args.steps, 2, torch, H, packed=True)
+        packed[name] = {"split": list(split), "ms_per_lt": round(ms_p / args.steps, 4),
+                        "lt_per_s": round(args.steps / wall_p, 2)}
+    packed["packed_poly_bytes"] = H.ckks_packed_poly_bytes(P)
+    packed["unpacked_poly_bytes"] = (prm.alpha + prm.max_level + 1) * prm.n * 8
+    out["packed_resident"] = packed
     print("single-LT legs done", flush=True, file=sys.stderr)
     same = same_shape_batch_leg(P, prm, level, th_split, 32, 5, torch, H)
     same["vs_plain_bsgs"] = round(same["lt_per_s"] / (1e3 / bs_ms), 3)

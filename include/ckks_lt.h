@@ -140,6 +140,7 @@ typedef struct {
   int stride;                    /* s; 0 reads as 1                          */
   int centre;                    /* c                                        */
   const double* const* slots;    /* host [n_diag] of device pointers or NULL */
+  int pt_packed;                 /* pt are packed (ckks_pack), TH-/DH-BSGS  */
 } ckks_lt_diags;
 
 /*
@@ -153,7 +154,31 @@ typedef struct {
   int count;
   const int32_t* rot;          /* host [count]: r (taken mod N/2)           */
   const uint64_t* const* key;  /* host [count] of device pointers           */
+  int packed;                  /* keys are packed (ckks_pack of the
+                                  beta_max * 2 polynomials of each key)     */
 } ckks_rotkeys;
+
+/*
+ * Packed storage of resident operands.  Keys and plaintexts are read once
+ * per use from HBM and dominate the bytes of the HBM-bound kernels; a limb
+ * of a prime below 2^40 holds values of at most 40 bits, so it is stored in
+ * 5N bytes instead of 8N: runs of 256 coefficients, each run its 256 32-bit
+ * low words (little-endian) followed by its 256 high bytes (1280 bytes per
+ * run); limbs of larger primes stay N 64-bit words.  A packed polynomial is
+ * the alpha + L + 1 limbs of the full PQ basis back to back (lower levels
+ * read a prefix); ckks_packed_poly_bytes gives its size.  ckks_pack converts
+ * count full PQ polynomials in (device [count][alpha+L+1][N] words, canonical)
+ * into out (device, count * packed bytes), on `stream`; in and out must not
+ * overlap.  A key is packed as its beta_max * 2 polynomials (count =
+ * 2 beta_max), a TH-BSGS plaintext as one.  The packed and unpacked forms
+ * give bit-identical LT results.  ckks_pack returns CKKS_E_INVALID_ARG for a
+ * null params, count outside 0..65535, a null buffer with count > 0, or
+ * overlapping buffers, CKKS_E_DEVICE if the launch fails, and CKKS_OK
+ * otherwise (count 0 does nothing); the caller owns both buffers, and the
+ * result is ready when `stream` reaches the launch.
+ */
+int ckks_packed_poly_bytes(const ckks_params* params, size_t* bytes);
+int ckks_pack(const ckks_params* params, int count, const uint64_t* in, void* out, void* stream);
 
 /* ---- the linear transformation ----------------------------------------- */
 #define CKKS_LT_NAIVE 0    /* diagonal method: sum_d Rot(ct, d) f_d           */

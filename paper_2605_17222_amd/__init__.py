@@ -43,7 +43,7 @@ EXPORTED = [
     "ckks_lt_batch_workspace_size", "ckks_lt_eval_batch", "ckks_lt_cost_model", "ckks_lt_autotune",
     "ckks_lt_predict", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit", "ckks_server_poll",
     "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats", "ckks_server_destroy",
-    "ckks_encode_workspace_size", "ckks_encode", "ckks_th_traffic_model",
+    "ckks_encode_workspace_size", "ckks_encode", "ckks_th_traffic_model", "ckks_packed_poly_bytes", "ckks_pack",
 ]
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
@@ -72,7 +72,7 @@ class Ct(ctypes.Structure):
 class Diags(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("n3", ctypes.c_int), ("n_diag", ctypes.c_int),
                 ("pt", ctypes.POINTER(ctypes.c_void_p)), ("pt_scale", ctypes.c_double), ("stride", ctypes.c_int),
-                ("centre", ctypes.c_int), ("slots", ctypes.POINTER(ctypes.c_void_p))]
+                ("centre", ctypes.c_int), ("slots", ctypes.POINTER(ctypes.c_void_p)), ("pt_packed", ctypes.c_int)]
 
 
 class EncodeItem(ctypes.Structure):
@@ -82,7 +82,7 @@ class EncodeItem(ctypes.Structure):
 
 class RotKeys(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int), ("rot", ctypes.POINTER(ctypes.c_int32)),
-                ("key", ctypes.POINTER(ctypes.c_void_p))]
+                ("key", ctypes.POINTER(ctypes.c_void_p)), ("packed", ctypes.c_int)]
 
 
 class LtCost(ctypes.Structure):
@@ -199,6 +199,8 @@ def lib() -> ctypes.CDLL:
         L.ckks_server_destroy.restype = None
         L.ckks_th_traffic_model.argtypes = [ctypes.c_int] * 8 + [ctypes.POINTER(ThParallelism),
                                                                  ctypes.POINTER(ThTraffic)]
+        L.ckks_packed_poly_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+        L.ckks_pack.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.ckks_encode_workspace_size.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.ckks_encode.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(EncodeItem), ctypes.c_double,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
@@ -279,14 +281,35 @@ def ckks_params_info(params: Params) -> Tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
+class Packed:
+    """A device buffer in the packed layout of ckks_pack (a uint8 tensor):
+    pass it wherever a key or a TH-BSGS plaintext goes."""
+
+    def __init__(self, t):
+        self.t = t
+
+    def data_ptr(self) -> int:
+        return self.t.data_ptr()
+
+
+def _all_packed(xs) -> bool:
+    xs = [x for x in xs if x is not None]
+    packed = [isinstance(x, Packed) for x in xs]
+    if any(packed) and not all(packed):
+        raise ValueError("packed and unpacked operands cannot be mixed in one call")
+    return bool(xs) and all(packed)
+
+
 def _diags(split: Sequence[int], pts: Sequence, pt_scale: float, stride: int = 1, centre: int = 0,
            onfly: bool = False):
     """onfly: pts holds slot vectors (complex128 device tensors of N/2
-    entries, or None) that the library encodes itself."""
+    entries, or None) that the library encodes itself; Packed plaintexts set
+    pt_packed."""
     n1, n2, n3 = (list(split) + [1, 1])[:3]
     arr = (ctypes.c_void_p * max(1, len(pts)))(*[_ptr(x) for x in pts])
     p = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
-    return Diags(n1, n2, n3, len(pts), None if onfly else p, pt_scale, stride, centre, p if onfly else None), arr
+    return Diags(n1, n2, n3, len(pts), None if onfly else p, pt_scale, stride, centre, p if onfly else None,
+                 0 if onfly else int(_all_packed(pts))), arr
 
 
 def _keys(keys: Optional[Dict[int, object]]):
@@ -295,7 +318,7 @@ def _keys(keys: Optional[Dict[int, object]]):
     r = (ctypes.c_int32 * max(1, len(rots)))(*rots)
     k = (ctypes.c_void_p * max(1, len(rots)))(*[_ptr(keys[x]) for x in rots])
     return RotKeys(len(rots), ctypes.cast(r, ctypes.POINTER(ctypes.c_int32)),
-                   ctypes.cast(k, ctypes.POINTER(ctypes.c_void_p))), (r, k)
+                   ctypes.cast(k, ctypes.POINTER(ctypes.c_void_p)), int(_all_packed(list(keys.values())))), (r, k)
 
 
 def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts: Sequence, algo: int,
@@ -493,6 +516,24 @@ def ckks_lt_autotune(log_n: int, level: int, alpha: int, algo: int, n_diag: int,
     _check(lib().ckks_lt_autotune(log_n, level, alpha, algo, n_diag, max_keys, r, ctypes.byref(a), ctypes.byref(b),
                                   ctypes.byref(c), ctypes.byref(t)), "ckks_lt_autotune")
     return (a.value, b.value, c.value), t.value
+
+
+def ckks_packed_poly_bytes(params: Params) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().ckks_packed_poly_bytes(params, ctypes.byref(out)), "ckks_packed_poly_bytes")
+    return out.value
+
+
+def ckks_pack(params: Params, polys, stream=None) -> Packed:
+    """Packs full PQ polynomials (device int64 tensor [..., alpha+L+1, N]; a
+    key [beta_max, 2, kmax, N] or a plaintext [kmax, N]) into a new Packed."""
+    import torch
+    kmax = params.alpha + params.max_level + 1
+    assert polys.is_contiguous() and polys.shape[-2:] == (kmax, params.n)
+    count = polys.numel() // (kmax * params.n)
+    out = torch.empty(count * ckks_packed_poly_bytes(params), dtype=torch.uint8, device=polys.device)
+    _check(lib().ckks_pack(params, count, _ptr(polys), _ptr(out), _stream(stream)), "ckks_pack")
+    return Packed(out)
 
 
 def ckks_encode_workspace_size(params: Params, count: int) -> int:

@@ -13,6 +13,7 @@
 // over j2 (length B).  Each sub-transform is an in-place radix-2 FFT in LDS.
 // Rounding is half away from zero.
 #include "internal.hpp"
+#include "modarith.hpp"
 
 namespace ckks {
 
@@ -147,6 +148,37 @@ hipError_t launch_encode_fft(const ckks_params* P, const EncArgs& a, hipStream_t
     case 16: return launch_enc<8, 7>(P, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+namespace {
+
+// Block (x, l, c): positions x*256.. of limb l of polynomial c.
+__global__ void __launch_bounds__(256)
+    pack_kernel(const uint64_t* __restrict__ in, uint8_t* __restrict__ out, const PrimeDev* __restrict__ primes,
+                int kmax, int log_n, uint64_t poly_bytes) {
+  const size_t n = (size_t)1 << log_n;
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int l = blockIdx.y;
+  const size_t c = blockIdx.z;
+  const PrimeDev& pr = primes[l];
+  const uint64_t v = in[(c * kmax + l) * n + p];
+  uint8_t* b = out + c * poly_bytes + pr.pk_off;
+  if (pr.narrow) {
+    uint8_t* c = b + (p / kPackChunk) * (5 * kPackChunk);
+    reinterpret_cast<uint32_t*>(c)[p % kPackChunk] = (uint32_t)v;
+    c[4 * kPackChunk + p % kPackChunk] = (uint8_t)(v >> 32);
+  } else {
+    reinterpret_cast<uint64_t*>(b)[p] = v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pack(const ckks_params* P, int count, const uint64_t* in, uint8_t* out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_kernel, dim3(P->n / 256, P->Kmax(), count), dim3(256), 0, s, in, out, P->d_primes,
+                     P->Kmax(), P->log_n, P->pk_poly_bytes);
+  return hipGetLastError();
 }
 
 }  // namespace ckks

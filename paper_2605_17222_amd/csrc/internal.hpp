@@ -33,7 +33,17 @@ struct PrimeDev {
   int pad;
   double qd, qinv_d;       // q and 1/q as doubles
   double ninv_d, ninv_q;   // N^-1 mod q as a double and divided by q
+  uint64_t pk_off;         // byte offset of this limb in a packed PQ polynomial
+  int narrow;              // q < 2^40: packed as a 32-bit and an 8-bit plane
+  int pk_pad;
 };
+
+// Packed storage of resident operands (keys, plaintexts): a limb of a prime
+// below 2^40 is N 32-bit low words followed by N 8-bit high bytes (5N
+// bytes); other limbs stay N 64-bit words.  A packed PQ polynomial is its
+// Kmax limbs back to back (limb i at PrimeDev::pk_off); lower levels read a
+// prefix.
+constexpr uint64_t kNarrowLimit = 1ull << 40;
 
 constexpr uint64_t kFpPrimeLimit = 1ull << 46;
 
@@ -117,8 +127,11 @@ struct KsArgs {
   const uint64_t* digits[kMaxDig];  // [beta_i][K_i][N] each
   const uint64_t* add[kMaxDig];     // [K_i][N], or Q-basis [K_i - alpha][N] to be multiplied by P, or null
   int add_pscaled[kMaxDig];
-  const uint64_t* key[kMaxKs];      // [beta_max][2][kmax][N]
+  const uint64_t* key[kMaxKs];      // [beta_max][2][kmax][N], or packed [beta_max][2] polynomials
+  int key_packed;                   // every key of the launch is packed (else none is)
+  uint64_t pk_poly_bytes;           // bytes of one packed PQ polynomial
   uint32_t gal_inv[kMaxKs];         // Galois element of -r: value at p is stored at auto_index(p, gal_inv)
+  int diag;                         // one-to-one: ndig == nkeys and only outputs (k, k) exist
   uint64_t* out_a[kMaxDig][kMaxKs];
   uint64_t* out_b[kMaxDig][kMaxKs];
 };
@@ -130,6 +143,8 @@ struct KsGatherArgs {
   int nk, beta, K, kmax;
   const uint64_t* digits[kMaxKs];  // [beta][K][N]
   const uint64_t* key[kMaxKs];
+  int key_packed;                  // every key of the launch is packed (else none is)
+  uint64_t pk_poly_bytes;
   const uint64_t* add[kMaxKs];     // u0_k [K][N]
   uint32_t gal[kMaxKs];            // Galois element of r_k
   uint64_t* c0;
@@ -140,6 +155,7 @@ struct MacArgs {
   int nm, nk, K, prime_off;
   int pscaled0;    // a[0], b[0] are Q-basis polynomials to be multiplied by P
   int accumulate;  // add into the outputs
+  int f_packed;    // f are packed PQ polynomials (prime_off = 0)
   const uint64_t* a[kMaxMacM];
   const uint64_t* b[kMaxMacM];
   const uint64_t* f[kMaxMacK][kMaxMacM];  // null = absent diagonal
@@ -194,6 +210,8 @@ hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGather
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
 hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
 hipError_t launch_encode_fft(const struct ::ckks_params* P, const EncArgs& a, hipStream_t s);
+// count full PQ polynomials [count][Kmax][N] -> packed [count][pk_poly_bytes].
+hipError_t launch_pack(const struct ::ckks_params* P, int count, const uint64_t* in, uint8_t* out, hipStream_t s);
 
 }  // namespace ckks
 
@@ -206,6 +224,7 @@ struct ckks_params {
   uint64_t* d_tw = nullptr;            // device [K_max][4][N]
   double* d_trow = nullptr;            // device [K_max][2][ntt_row_tables_size]
   ckks::BConvPlan* d_plans = nullptr;  // device plan table
+  uint64_t pk_poly_bytes = 0;          // bytes of one packed PQ polynomial (Kmax limbs)
   // Encoding tables (N/2 entries each): perm[j] = t with 5^t = 4 j + 1 mod 2N;
   // enc_tw[e] = e^(-2 pi i e / (N/2)); enc_zinv[k] = zeta^-k / (N/2), as (re, im).
   int* d_enc_perm = nullptr;

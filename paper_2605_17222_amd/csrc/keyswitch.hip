@@ -29,7 +29,59 @@ constexpr int kThreads = 256;
 // cached data, which lifts the achieved read bandwidth on gfx950.
 __device__ __forceinline__ uint64_t ld_nt(const uint64_t* p) { return __builtin_nontemporal_load(p); }
 
-template <int NDIG>
+// Bytes between the polynomials of a key [beta_max][2] (index 2 b + s):
+// packed polynomials of pk_bytes each, or [kmax][N] words each.
+__device__ __forceinline__ size_t poly_stride(bool packed, uint64_t pk_bytes, int kmax, size_t n) {
+  return packed ? pk_bytes : (size_t)kmax * n * 8;
+}
+
+// Key k's limb l of polynomials (2 b, 2 b + 1), b < kbeta, at position p.
+template <bool NARROW>
+__device__ __forceinline__ void ld_key(uint64_t (&k0)[kMaxBeta], uint64_t (&k1)[kMaxBeta], const uint8_t* base,
+                                       size_t stride, int kbeta, size_t p, size_t n) {
+#pragma unroll
+  for (int b = 0; b < kMaxBeta; ++b) {
+    if (b < kbeta) {
+      k0[b] = ld_word<NARROW>(base + (2 * b) * stride, p, n);
+      k1[b] = ld_word<NARROW>(base + (2 * b + 1) * stride, p, n);
+    }
+  }
+}
+
+// The keys of a key-switch launch against the digits d (limb l, position p):
+// key k's product with digit set i is written at phi_k's position of p.
+template <int NDIG, bool PACKED, bool NARROW>
+__device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n, int log_n,
+                                        const uint64_t (&d)[NDIG][kMaxBeta], const uint64_t (&addv)[NDIG]) {
+  const uint64_t q = pr.q;
+  const size_t lo = limb_off(l, n, PACKED, pr);
+  const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
+  for (int k = 0; k < a.nkeys; ++k) {
+    uint64_t k0[kMaxBeta], k1[kMaxBeta];
+    ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.kbeta, p, n);
+    const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
+#pragma unroll
+    for (int i = 0; i < NDIG; ++i) {
+      uint64_t* oa = a.out_a[i][k];
+      if (!oa || l >= a.K[i]) continue;
+      uint64_t* ob = a.out_b[i][k];
+      U128 x = {0, 0}, y = {0, 0};
+#pragma unroll
+      for (int b = 0; b < kMaxBeta; ++b) {
+        if (b < a.beta[i]) {
+          add128(x, mul_wide(d[i][b], k0[b]));
+          add128(y, mul_wide(d[i][b], k1[b]));
+        }
+      }
+      oa[o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv[i], q);
+      ob[o] = barrett128(y, q, pr.r_lo, pr.r_hi);
+    }
+  }
+}
+
+// PACKED: every key of the launch is stored packed.  Limb l is uniform over a
+// block, so the narrow/wide choice is made once, outside the key loop.
+template <int NDIG, bool PACKED>
 __global__ void __launch_bounds__(kThreads)
     ks_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
@@ -53,88 +105,136 @@ __global__ void __launch_bounds__(kThreads)
         addv[i] = ld_nt(a.add[i] + (size_t)l * n + p);
     }
   }
-  for (int k = 0; k < a.nkeys; ++k) {
-    const uint64_t* __restrict__ key = a.key[k];
-    uint64_t k0[kMaxBeta], k1[kMaxBeta];
-#pragma unroll
-    for (int b = 0; b < kMaxBeta; ++b) {
-      if (b < a.kbeta) {
-        k0[b] = ld_nt(key + (((size_t)b * 2 + 0) * a.kmax + l) * n + p);
-        k1[b] = ld_nt(key + (((size_t)b * 2 + 1) * a.kmax + l) * n + p);
-      }
-    }
-    const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
-#pragma unroll
-    for (int i = 0; i < NDIG; ++i) {
-      uint64_t* oa = a.out_a[i][k];
-      if (!oa || l >= a.K[i]) continue;
-      uint64_t* ob = a.out_b[i][k];
-      U128 x = {0, 0}, y = {0, 0};
-#pragma unroll
-      for (int b = 0; b < kMaxBeta; ++b) {
-        if (b < a.beta[i]) {
-          add128(x, mul_wide(d[i][b], k0[b]));
-          add128(y, mul_wide(d[i][b], k1[b]));
-        }
-      }
-      oa[o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv[i], q);
-      ob[o] = barrett128(y, q, pr.r_lo, pr.r_hi);
-    }
+  if constexpr (PACKED) {
+    if (pr.narrow)
+      ks_keys<NDIG, true, true>(a, pr, l, p, n, log_n, d, addv);
+    else
+      ks_keys<NDIG, true, false>(a, pr, l, p, n, log_n, d, addv);
+  } else {
+    ks_keys<NDIG, false, false>(a, pr, l, p, n, log_n, d, addv);
   }
 }
 
 template <int NDIG>
 hipError_t launch_ks(const ckks_params* P, const KsArgs& a, hipStream_t s) {
   dim3 grid(P->n / kThreads, a.maxK);
-  hipLaunchKernelGGL((ks_kernel<NDIG>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  if (a.key_packed)
+    hipLaunchKernelGGL((ks_kernel<NDIG, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  else
+    hipLaunchKernelGGL((ks_kernel<NDIG, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
   return hipGetLastError();
 }
 
+// One-to-one launches (key k with digit set k only, as in the separate
+// giant-step rotations of plain BSGS): each key's digits are loaded inside
+// the key loop, so only one digit set is live and occupancy stays high.
+template <bool PACKED, bool NARROW>
+__device__ __forceinline__ void diag_keys(const KsArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n, int log_n,
+                                          int alpha) {
+  const uint64_t q = pr.q;
+  const size_t lo = limb_off(l, n, PACKED, pr);
+  const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
+  for (int k = 0; k < a.nkeys; ++k) {
+    if (l >= a.K[k]) continue;
+    const int beta = a.beta[k];
+    uint64_t k0[kMaxBeta], k1[kMaxBeta];
+    ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, beta, p, n);
+    U128 x = {0, 0}, y = {0, 0};
+#pragma unroll
+    for (int b = 0; b < kMaxBeta; ++b) {
+      if (b < beta) {
+        const uint64_t d = ld_nt(a.digits[k] + ((size_t)b * a.K[k] + l) * n + p);
+        add128(x, mul_wide(d, k0[b]));
+        add128(y, mul_wide(d, k1[b]));
+      }
+    }
+    uint64_t addv = 0;
+    if (a.add[k]) {
+      if (a.add_pscaled[k])
+        addv = (l < alpha) ? 0 : shoup(ld_nt(a.add[k] + (size_t)(l - alpha) * n + p), pr.pmod, pr.pmod_sh, q);
+      else
+        addv = ld_nt(a.add[k] + (size_t)l * n + p);
+    }
+    const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
+    a.out_a[k][k][o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
+    a.out_b[k][k][o] = barrett128(y, q, pr.r_lo, pr.r_hi);
+  }
+}
+
+template <bool PACKED>
 __global__ void __launch_bounds__(kThreads)
-    ks_gather_kernel(KsGatherArgs a, const PrimeDev* __restrict__ primes, int log_n) {
+    ks_diag_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
   const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
   const int l = blockIdx.y;
   const PrimeDev& pr = primes[l];
+  if constexpr (PACKED) {
+    if (pr.narrow)
+      diag_keys<true, true>(a, pr, l, p, n, log_n, alpha);
+    else
+      diag_keys<true, false>(a, pr, l, p, n, log_n, alpha);
+  } else {
+    diag_keys<false, false>(a, pr, l, p, n, log_n, alpha);
+  }
+}
+
+// The gather's key loop (limb l, output position p).
+template <bool PACKED, bool NARROW>
+__device__ __forceinline__ void gather_keys(const KsGatherArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n,
+                                            int log_n, uint64_t& c0, uint64_t& c1) {
   const uint64_t q = pr.q;
-  const size_t o = (size_t)l * n + p;
-  uint64_t c0 = a.c0[o], c1 = a.c1[o];
+  const size_t lo = limb_off(l, n, PACKED, pr);
+  const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
   for (int k = 0; k < a.nk; ++k) {
-    const size_t s = (size_t)l * n + auto_index(p, a.gal[k], log_n);
-    const uint64_t* __restrict__ key = a.key[k];
+    const uint32_t src = auto_index(p, a.gal[k], log_n);
+    const size_t s = (size_t)l * n + src;
+    uint64_t k0[kMaxBeta], k1[kMaxBeta];
+    ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.beta, src, n);
     const uint64_t* __restrict__ dg = a.digits[k];
     U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b) {
       if (b < a.beta) {
         const uint64_t d = ld_nt(dg + (size_t)b * a.K * n + s);
-        add128(x, mul_wide(d, ld_nt(key + ((size_t)b * 2 + 0) * a.kmax * n + s)));
-        add128(y, mul_wide(d, ld_nt(key + ((size_t)b * 2 + 1) * a.kmax * n + s)));
+        add128(x, mul_wide(d, k0[b]));
+        add128(y, mul_wide(d, k1[b]));
       }
     }
     c0 = add_mod(c0, add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), ld_nt(a.add[k] + s), q), q);
     c1 = add_mod(c1, barrett128(y, q, pr.r_lo, pr.r_hi), q);
   }
+}
+
+template <bool PACKED>
+__global__ void __launch_bounds__(kThreads)
+    ks_gather_kernel(KsGatherArgs a, const PrimeDev* __restrict__ primes, int log_n) {
+  const size_t n = (size_t)1 << log_n;
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const PrimeDev& pr = primes[l];
+  const size_t o = (size_t)l * n + p;
+  uint64_t c0 = a.c0[o], c1 = a.c1[o];
+  if constexpr (PACKED) {
+    if (pr.narrow)
+      gather_keys<true, true>(a, pr, l, p, n, log_n, c0, c1);
+    else
+      gather_keys<true, false>(a, pr, l, p, n, log_n, c0, c1);
+  } else {
+    gather_keys<false, false>(a, pr, l, p, n, log_n, c0, c1);
+  }
   a.c0[o] = c0;
   a.c1[o] = c1;
 }
 
-// m-outer loop: (a_m, b_m) and the NK plaintexts of index m are loaded
-// together and folded into NK pairs of 128-bit accumulators, so few values are
-// live and many loads are in flight per wavefront.
-template <int NK>
-__global__ void __launch_bounds__(kThreads)
-    mac_kernel(MacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
-  const size_t n = (size_t)1 << log_n;
-  const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
-  const int l = blockIdx.y;
-  const PrimeDev& pr = primes[l + a.prime_off];
+// The m-outer loop of the MAC for one limb: (a_m, b_m) and the NK plaintexts
+// of index m are loaded together and folded into NK pairs of 128-bit
+// accumulators, so few values are live and many loads are in flight per
+// wavefront.  fo: byte offset of the limb within each plaintext.
+template <int NK, bool NARROW, typename PrimeT>
+__device__ __forceinline__ void mac_loop(const MacArgs& a, const PrimeT& pr, int l, size_t p, size_t n, int alpha,
+                                         size_t fo, U128 (&x)[NK], U128 (&y)[NK]) {
   const uint64_t q = pr.q;
   const size_t off = (size_t)l * n + p;
-
-  U128 x[NK], y[NK];
-#pragma unroll
-  for (int k = 0; k < NK; ++k) x[k] = y[k] = U128{0, 0};
 #pragma unroll 2
   for (int m = 0; m < a.nm; ++m) {
     uint64_t av, bv;
@@ -151,12 +251,32 @@ __global__ void __launch_bounds__(kThreads)
     for (int k = 0; k < NK; ++k) {
       const uint64_t* __restrict__ fp = a.f[k][m];
       if (fp) {
-        const uint64_t f = ld_nt(fp + off);
+        const uint64_t f = ld_word<NARROW>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n);
         add128(x[k], mul_wide(av, f));
         add128(y[k], mul_wide(bv, f));
       }
     }
   }
+}
+
+template <int NK>
+__global__ void __launch_bounds__(kThreads)
+    mac_kernel(MacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
+  const size_t n = (size_t)1 << log_n;
+  const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const PrimeDev& pr = primes[l + a.prime_off];
+  const uint64_t q = pr.q;
+  const size_t off = (size_t)l * n + p;
+  const size_t fo = limb_off(l, n, a.f_packed != 0, pr);
+
+  U128 x[NK], y[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) x[k] = y[k] = U128{0, 0};
+  if (a.f_packed && pr.narrow)
+    mac_loop<NK, true>(a, pr, l, p, n, alpha, fo, x, y);
+  else
+    mac_loop<NK, false>(a, pr, l, p, n, alpha, fo, x, y);
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     uint64_t xr = barrett128(x[k], q, pr.r_lo, pr.r_hi);
@@ -193,6 +313,13 @@ __global__ void __launch_bounds__(kThreads)
 
 }  // namespace
 
+// Bytes of the first `count` limbs of a PQ polynomial, packed or not.
+static double limb_bytes(const ckks_params* P, int count, bool packed) {
+  double b = 0;
+  for (int i = 0; i < count; ++i) b += (packed && P->primes[i] < kNarrowLimit ? 5.0 : 8.0) * P->n;
+  return b;
+}
+
 hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s) {
   double words = 0;
   for (int i = 0; i < a.ndig; ++i) {
@@ -200,8 +327,17 @@ hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s
     for (int k = 0; k < a.nkeys; ++k) per += a.out_a[i][k] ? 2 : 0;
     words += per * a.K[i];
   }
-  words += 2.0 * a.kbeta * a.nkeys * a.maxK;
-  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * P->n * 8);
+  double key_bytes = 0;
+  for (int k = 0; k < a.nkeys; ++k) key_bytes += 2.0 * a.kbeta * limb_bytes(P, a.maxK, a.key_packed);
+  ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * P->n * 8 + key_bytes);
+  if (a.diag) {
+    dim3 grid(P->n / kThreads, a.maxK);
+    if (a.key_packed)
+      hipLaunchKernelGGL(ks_diag_kernel<true>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+    else
+      hipLaunchKernelGGL(ks_diag_kernel<false>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+    return hipGetLastError();
+  }
   switch (a.ndig) {
     case 1: return launch_ks<1>(P, a, s);
     case 2: return launch_ks<2>(P, a, s);
@@ -216,10 +352,14 @@ hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s
 }
 
 hipError_t launch_keyswitch_gather(const ckks_params* P, const KsGatherArgs& a, hipStream_t s) {
-  const double words = (double)a.K * P->n * (4.0 + a.nk * (3.0 * a.beta + 1));
-  ProfScope prof(CKKS_KERNEL_KEYSWITCH_GATHER, s, words * 8);
+  double bytes = (double)a.K * P->n * (4.0 + a.nk * (a.beta + 1)) * 8;
+  bytes += a.nk * 2.0 * a.beta * limb_bytes(P, a.K, a.key_packed);
+  ProfScope prof(CKKS_KERNEL_KEYSWITCH_GATHER, s, bytes);
   dim3 grid(P->n / kThreads, a.K);
-  hipLaunchKernelGGL(ks_gather_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  if (a.key_packed)
+    hipLaunchKernelGGL(ks_gather_kernel<true>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  else
+    hipLaunchKernelGGL(ks_gather_kernel<false>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
   return hipGetLastError();
 }
 
@@ -227,8 +367,8 @@ hipError_t launch_ptmac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
   int nf = 0;
   for (int k = 0; k < a.nk; ++k)
     for (int m = 0; m < a.nm; ++m) nf += a.f[k][m] ? 1 : 0;
-  const double words = (double)a.K * P->n * (2.0 * a.nm + nf + 2.0 * a.nk * (a.accumulate ? 2 : 1));
-  ProfScope prof(CKKS_KERNEL_PTMAC, s, words * 8);
+  const double words = (double)a.K * P->n * (2.0 * a.nm + 2.0 * a.nk * (a.accumulate ? 2 : 1));
+  ProfScope prof(CKKS_KERNEL_PTMAC, s, words * 8 + nf * limb_bytes(P, a.K, a.f_packed && a.prime_off == 0));
   switch (a.nk) {
     case 1: return launch_mac<1>(P, a, s);
     case 2: return launch_mac<2>(P, a, s);

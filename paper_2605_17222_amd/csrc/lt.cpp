@@ -233,6 +233,7 @@ struct KsTask {
   uint32_t gal_inv;
   uint64_t* oa;
   uint64_t* ob;
+  bool key_packed;  // the key is stored packed
 };
 
 // Packs tasks into launches of at most kMaxKs distinct keys and kMaxDig
@@ -242,42 +243,53 @@ struct KsTask {
 void keyswitch(Run& R, const std::vector<KsTask>& tasks) {
   if (!R.live() || tasks.empty()) return;
   const ckks_params* P = R.P;
-  std::vector<const uint64_t*> keys;
-  for (const KsTask& t : tasks)
-    if (std::find(keys.begin(), keys.end(), t.key) == keys.end()) keys.push_back(t.key);
-  for (size_t k0 = 0; k0 < keys.size(); k0 += kMaxKs) {
-    const size_t k1 = std::min(keys.size(), k0 + kMaxKs);
-    std::vector<const uint64_t*> digs;  // digit sets used with this chunk of keys
-    for (const KsTask& t : tasks) {
-      const size_t ki = std::find(keys.begin(), keys.end(), t.key) - keys.begin();
-      if (ki < k0 || ki >= k1) continue;
-      if (std::find(digs.begin(), digs.end(), t.digits) == digs.end()) digs.push_back(t.digits);
-    }
-    for (size_t i0 = 0; i0 < digs.size(); i0 += kMaxDig) {
-      const size_t i1 = std::min(digs.size(), i0 + kMaxDig);
-      KsArgs ka;
-      memset(&ka, 0, sizeof(ka));
-      ka.kmax = P->Kmax();
-      ka.nkeys = (int)(k1 - k0);
-      ka.ndig = (int)(i1 - i0);
-      for (size_t k = k0; k < k1; ++k) ka.key[k - k0] = keys[k];
+  // packed and unpacked keys go to separate launches
+  for (int pk = 0; pk < 2; ++pk) {
+    std::vector<const uint64_t*> keys;
+    for (const KsTask& t : tasks)
+      if ((t.key_packed ? 1 : 0) == pk && std::find(keys.begin(), keys.end(), t.key) == keys.end())
+        keys.push_back(t.key);
+    for (size_t k0 = 0; k0 < keys.size(); k0 += kMaxKs) {
+      const size_t k1 = std::min(keys.size(), k0 + kMaxKs);
+      std::vector<const uint64_t*> digs;  // digit sets used with this chunk of keys
       for (const KsTask& t : tasks) {
         const size_t ki = std::find(keys.begin(), keys.end(), t.key) - keys.begin();
-        const size_t di = std::find(digs.begin(), digs.end(), t.digits) - digs.begin();
-        if (ki < k0 || ki >= k1 || di < i0 || di >= i1) continue;
-        const int i = (int)(di - i0), k = (int)(ki - k0);
-        ka.digits[i] = t.digits;
-        ka.K[i] = P->K(t.level);
-        ka.beta[i] = P->beta(t.level);
-        ka.add[i] = t.add;
-        ka.add_pscaled[i] = t.pscaled ? 1 : 0;
-        ka.gal_inv[k] = t.gal_inv;
-        ka.out_a[i][k] = t.oa;
-        ka.out_b[i][k] = t.ob;
-        ka.kbeta = std::max(ka.kbeta, ka.beta[i]);
-        ka.maxK = std::max(ka.maxK, ka.K[i]);
+        if (ki < k0 || ki >= k1) continue;
+        if (std::find(digs.begin(), digs.end(), t.digits) == digs.end()) digs.push_back(t.digits);
       }
-      R.check(launch_keyswitch(P, ka, R.s));
+      for (size_t i0 = 0; i0 < digs.size(); i0 += kMaxDig) {
+        const size_t i1 = std::min(digs.size(), i0 + kMaxDig);
+        KsArgs ka;
+        memset(&ka, 0, sizeof(ka));
+        ka.kmax = P->Kmax();
+        ka.pk_poly_bytes = P->pk_poly_bytes;
+        ka.key_packed = pk;
+        ka.nkeys = (int)(k1 - k0);
+        ka.ndig = (int)(i1 - i0);
+        for (size_t k = k0; k < k1; ++k) ka.key[k - k0] = keys[k];
+        int ntask = 0, ndiag = 0;
+        for (const KsTask& t : tasks) {
+          const size_t ki = std::find(keys.begin(), keys.end(), t.key) - keys.begin();
+          const size_t di = std::find(digs.begin(), digs.end(), t.digits) - digs.begin();
+          if (ki < k0 || ki >= k1 || di < i0 || di >= i1) continue;
+          const int i = (int)(di - i0), k = (int)(ki - k0);
+          ka.digits[i] = t.digits;
+          ka.K[i] = P->K(t.level);
+          ka.beta[i] = P->beta(t.level);
+          ka.add[i] = t.add;
+          ka.add_pscaled[i] = t.pscaled ? 1 : 0;
+          ka.gal_inv[k] = t.gal_inv;
+          ka.out_a[i][k] = t.oa;
+          ka.out_b[i][k] = t.ob;
+          ka.kbeta = std::max(ka.kbeta, ka.beta[i]);
+          ka.maxK = std::max(ka.maxK, ka.K[i]);
+          ++ntask;
+          ndiag += i == k;
+        }
+        // several keys, each with its own digit set only
+        ka.diag = ka.ndig > 1 && ka.ndig == ka.nkeys && ntask == ka.nkeys && ndiag == ntask;
+        R.check(launch_keyswitch(P, ka, R.s));
+      }
     }
   }
 }
@@ -347,8 +359,9 @@ struct MacEnc {
 // outs[k] = sum_m terms[m] * f[k], over nlimbs limbs starting at prime_off.
 // Terms with z get their plaintexts encoded right before the launch that
 // reads them, into workspace that the next launch reuses.
+// f_packed: the resident plaintexts are packed PQ polynomials (prime_off 0).
 void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms, const std::vector<uint64_t*>& o0,
-           const std::vector<uint64_t*>& o1, const MacEnc* enc = nullptr) {
+           const std::vector<uint64_t*>& o1, const MacEnc* enc = nullptr, bool f_packed = false) {
   const int nk_all = (int)o0.size();
   for (int k0 = 0; k0 < nk_all; k0 += kMaxMacK) {
     const int nk = std::min(kMaxMacK, nk_all - k0);
@@ -360,6 +373,7 @@ void ptmac(Run& R, int nlimbs, int prime_off, const std::vector<MacTerm>& terms,
       ma.K = nlimbs;
       ma.prime_off = prime_off;
       ma.accumulate = first ? 0 : 1;
+      ma.f_packed = f_packed ? 1 : 0;
       const size_t mark = R.ws.mark();
       std::vector<EncItem> pts;
       int nm = 0;
@@ -408,6 +422,7 @@ void automorph(Run& R, int nlimbs, int prime_off, uint32_t gal, const uint64_t* 
 struct KeySet {
   std::map<long, const uint64_t*> m;
   long S = 0;
+  bool packed = false;  // every key of the set is stored packed
   const uint64_t* get(Run& R, long r) const {
     const long rr = ((r % S) + S) % S;
     auto it = m.find(rr);
@@ -453,7 +468,7 @@ void rotate(Run& R, int level, const std::vector<RotJob>& jobs, const KeySet& ks
       dc.push_back({level, J.c1, D[t]});
       md.push_back({level, X[t], Xq[t]});
       md.push_back({level, Y[t], Yq[t]});
-      tasks.push_back(KsTask{D[t], level, nullptr, false, ks.get(R, J.r), 1u, X[t], Y[t]});
+      tasks.push_back(KsTask{D[t], level, nullptr, false, ks.get(R, J.r), 1u, X[t], Y[t], ks.packed});
     }
     decompose(R, dc);
     keyswitch(R, tasks);
@@ -475,6 +490,7 @@ struct Diag {
   const uint64_t* const* pt = nullptr;
   const double* const* z = nullptr;
   double zscale = 0;
+  bool packed = false;  // pt are packed PQ polynomials
   bool has(int m) const { return m >= 0 && m < n && (z ? z[m] != nullptr : pt[m] != nullptr); }
 };
 
@@ -577,7 +593,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
       for (int i = 1; i < it.n1; ++i)
         if (it.used_i[i])
           tasks.push_back(KsTask{it.Dg[0], it.level, it.c0, true, it.ks->get(R, it.stride * i),
-                                 galois(P, -it.stride * i), it.A[i], it.B[i]});
+                                 galois(P, -it.stride * i), it.A[i], it.B[i], it.ks->packed});
     keyswitch(R, tasks);
   }
   // Lines 6-7: d_i = Decompose(ModDown(b_i)), every i at once.
@@ -603,7 +619,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
           if (!it.mid_i[i] || !it.used_m[m]) continue;
           const long r = it.stride * it.n1 * j;
           tasks.push_back(KsTask{it.Dg[i], it.level, i == 0 ? it.c0 : it.A[i], i == 0, it.ks->get(R, r),
-                                 galois(P, -r), it.A[m], it.B[m]});
+                                 galois(P, -r), it.A[m], it.B[m], it.ks->packed});
         }
     keyswitch(R, tasks);
   }
@@ -639,7 +655,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
       o1.push_back(k >= 0 ? it.U1[k] : it.acc1);
       enc.rot.push_back(k >= 0 ? -it.giant(P, k) : 0);  // f^ = encode(rot(diag, -G_k))
     }
-    ptmac(R, K, 0, terms, o0, o1, it.D.z ? &enc : nullptr);
+    ptmac(R, K, 0, terms, o0, o1, it.D.z ? &enc : nullptr, it.D.packed);
   }
   // Lines 13-18: outer rotations by G_k: ModDown and Decompose of every
   // (item, k) at once, then per item one gather kernel adds
@@ -664,6 +680,8 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
         ga.beta = P->beta(it.level);
         ga.K = P->K(it.level);
         ga.kmax = P->Kmax();
+        ga.pk_poly_bytes = P->pk_poly_bytes;
+        ga.key_packed = it.ks->packed ? 1 : 0;
         ga.c0 = it.acc0;
         ga.c1 = it.acc1;
         for (size_t t = k0; t < std::min(kk.size(), k0 + kMaxKs); ++t) {
@@ -826,6 +844,10 @@ int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* dia
   if (diags->n_diag < 0 || (diags->n_diag > 0 && !diags->pt && !diags->slots) || (diags->pt && diags->slots))
     return CKKS_E_INVALID_ARG;
   if (diags->slots && (!(diags->pt_scale > 0) || !std::isfinite(diags->pt_scale))) return CKKS_E_INVALID_ARG;
+  if (diags->pt_packed) {
+    if (diags->slots) return CKKS_E_INVALID_ARG;
+    if (algo != CKKS_LT_TH_BSGS && algo != CKKS_LT_DH_BSGS) return CKKS_E_UNSUPPORTED;  // PQ-basis plaintexts only
+  }
   if (check_buffers) {
     if (!in->c0 || !in->c1 || !out->c0 || !out->c1) return CKKS_E_INVALID_ARG;
     const size_t N = (size_t)P->n;
@@ -836,6 +858,7 @@ int check_item(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* dia
     if (overlap(out->c0, out_bytes, out->c1, out_bytes)) return CKKS_E_INVALID_ARG;
   }
   ks->S = P->n / 2;
+  ks->packed = keys && keys->packed;
   if (keys) {
     if (keys->count < 0 || (keys->count > 0 && (!keys->rot || !keys->key))) return CKKS_E_INVALID_ARG;
     for (int i = 0; i < keys->count; ++i) ks->m[((keys->rot[i] % ks->S) + ks->S) % ks->S] = keys->key[i];
@@ -886,6 +909,7 @@ ThItem th_item(const ckks_ct* in, const ckks_lt_diags* d, const KeySet* ks, ckks
   it.D.pt = d->pt;
   it.D.z = d->slots;
   it.D.zscale = d->pt_scale;
+  it.D.packed = d->pt_packed != 0;
   it.ks = ks;
   it.o0 = out->c0;
   it.o1 = out->c1;
@@ -1074,6 +1098,22 @@ int ckks_encode(const ckks_params* P, int count, const ckks_encode_item* items, 
   }
 }
 
+int ckks_packed_poly_bytes(const ckks_params* P, size_t* bytes) {
+  if (!P || !bytes) return CKKS_E_INVALID_ARG;
+  *bytes = (size_t)P->pk_poly_bytes;
+  return CKKS_OK;
+}
+
+int ckks_pack(const ckks_params* P, int count, const uint64_t* in, void* out, void* stream) {
+  if (!P || count < 0 || count > 65535 || (count > 0 && (!in || !out))) return CKKS_E_INVALID_ARG;
+  if (count == 0) return CKKS_OK;
+  const size_t in_bytes = (size_t)count * P->Kmax() * P->n * 8, out_bytes = (size_t)count * P->pk_poly_bytes;
+  if (overlap(in, in_bytes, out, out_bytes)) return CKKS_E_INVALID_ARG;
+  DeviceGuard dg(P->device);
+  return launch_pack(P, count, in, static_cast<uint8_t*>(out), (hipStream_t)stream) == hipSuccess ? CKKS_OK
+                                                                                                   : CKKS_E_DEVICE;
+}
+
 static int batch_common(const ckks_params* P, int count, ckks_lt_item* items, int algo, void* ws, size_t ws_bytes,
                         void* stream, bool plan_only, size_t* need) {
   if (!P || count < 0 || (count > 0 && !items)) return CKKS_E_INVALID_ARG;
@@ -1227,7 +1267,7 @@ int ckks_op_keyswitch(const ckks_params* P, int level, const uint64_t* digits, c
   if (!P || !digits || !key || !out_a || !out_b || level < 0 || level > P->L) return CKKS_E_INVALID_ARG;
   DeviceGuard dg(P->device);
   Run R = make_run(P, stream, false, nullptr);
-  keyswitch(R, {KsTask{digits, level, add, false, key, galois(P, -(long)rot), out_a, out_b}});
+  keyswitch(R, {KsTask{digits, level, add, false, key, galois(P, -(long)rot), out_a, out_b, false}});
   return R.err;
 }
 

@@ -146,4 +146,42 @@ __device__ __forceinline__ uint32_t auto_index(uint32_t p, uint32_t g, int log_n
   return bitrev((e - 1u) >> 1, log_n);
 }
 
+// Packed narrow limbs are runs of kPackChunk coefficients: the run's 32-bit
+// low words, then its 8-bit high bytes (5 kPackChunk bytes), so one limb is a
+// single contiguous stream.
+constexpr size_t kPackChunk = 256;
+
+#ifdef __HIPCC__
+// Limb l (prime pr) of a polynomial at `poly`, stored packed (the limb starts
+// at byte pr.pk_off; a narrow prime's limb is in runs as above) or as
+// [limbs][N] 64-bit words.  Both are uniform over a block whose limb index is
+// uniform, so a kernel branches once on `narrow` and then issues straight-line
+// loads.
+struct LimbRef {
+  const uint8_t* b;  // first byte of the limb
+  bool narrow;       // 32 + 8-bit planes (else N 64-bit words)
+};
+template <typename PrimeT>  // the library's per-prime table entry (pk_off, narrow)
+__device__ __forceinline__ size_t limb_off(int l, size_t n, bool packed, const PrimeT& pr) {
+  return packed ? (size_t)pr.pk_off : (size_t)l * n * 8;
+}
+template <typename PrimeT>
+__device__ __forceinline__ LimbRef limb_ref(const void* poly, int l, size_t n, bool packed, const PrimeT& pr) {
+  return {reinterpret_cast<const uint8_t*>(poly) + limb_off(l, n, packed, pr), packed && pr.narrow};
+}
+// Word p of a limb; non-temporal loads, these operands are read once per launch.
+template <bool NARROW>
+__device__ __forceinline__ uint64_t ld_word(const uint8_t* b, size_t p, size_t n) {
+  if constexpr (NARROW) {
+    const uint8_t* c = b + (p / kPackChunk) * (5 * kPackChunk);
+    const size_t r = p % kPackChunk;
+    const uint64_t lo = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(c) + r);
+    const uint64_t hi = __builtin_nontemporal_load(c + 4 * kPackChunk + r);
+    return lo | (hi << 32);
+  } else {
+    return __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(b) + p);
+  }
+}
+#endif
+
 }  // namespace ckks

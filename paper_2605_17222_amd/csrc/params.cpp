@@ -248,6 +248,10 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
     for (int k = 0; k < P->alpha; ++k) Pm = mm(Pm, P->primes[k] % q, q);
     c.pmod = i < P->alpha ? 0 : Pm;
     c.pmod_sh = shoup_of(c.pmod, q);
+    c.narrow = q < kNarrowLimit ? 1 : 0;
+    c.pk_off = P->pk_poly_bytes;
+    c.pk_pad = 0;
+    P->pk_poly_bytes += (uint64_t)n * (c.narrow ? 5 : 8);
   }
 
   // Basis-conversion plans.

@@ -339,6 +339,7 @@ int ckks_server_add_ring(ckks_server* S, const ckks_params* params, const ckks_r
     R.keys.count = keys->count;
     R.keys.rot = R.rot.data();
     R.keys.key = R.key.data();
+    R.keys.packed = keys->packed;
     *ring_id = (int)S->rings.size() - 1;
     return CKKS_OK;
   } catch (...) {
