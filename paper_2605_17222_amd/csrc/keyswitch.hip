@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kThreads)
 // of index m are loaded together and folded into NK pairs of 128-bit
 // accumulators, so few values are live and many loads are in flight per
 // wavefront.  fo: byte offset of the limb within each plaintext.
-template <int NK, bool NARROW, typename PrimeT>
+template <int NK, bool PACKED, bool NARROW, typename PrimeT>
 __device__ __forceinline__ void mac_loop(const MacArgs& a, const PrimeT& pr, int l, size_t p, size_t n, int alpha,
                                          size_t fo, U128 (&x)[NK], U128 (&y)[NK]) {
   const uint64_t q = pr.q;
@@ -251,7 +251,11 @@ __device__ __forceinline__ void mac_loop(const MacArgs& a, const PrimeT& pr, int
     for (int k = 0; k < NK; ++k) {
       const uint64_t* __restrict__ fp = a.f[k][m];
       if (fp) {
-        const uint64_t f = ld_word<NARROW>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n);
+        uint64_t f;
+        if constexpr (PACKED)
+          f = ld_word<NARROW>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n);
+        else
+          f = ld_nt(fp + off);  // the word offset the (a_m, b_m) loads use
         add128(x[k], mul_wide(av, f));
         add128(y[k], mul_wide(bv, f));
       }
@@ -259,7 +263,9 @@ __device__ __forceinline__ void mac_loop(const MacArgs& a, const PrimeT& pr, int
   }
 }
 
-template <int NK>
+// F_PACKED: the plaintexts are packed.  The unpacked instantiation holds the
+// wide path only (the second path would cost registers and occupancy).
+template <int NK, bool F_PACKED>
 __global__ void __launch_bounds__(kThreads)
     mac_kernel(MacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
@@ -268,15 +274,19 @@ __global__ void __launch_bounds__(kThreads)
   const PrimeDev& pr = primes[l + a.prime_off];
   const uint64_t q = pr.q;
   const size_t off = (size_t)l * n + p;
-  const size_t fo = limb_off(l, n, a.f_packed != 0, pr);
+  const size_t fo = limb_off(l, n, F_PACKED, pr);
 
   U128 x[NK], y[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) x[k] = y[k] = U128{0, 0};
-  if (a.f_packed && pr.narrow)
-    mac_loop<NK, true>(a, pr, l, p, n, alpha, fo, x, y);
-  else
-    mac_loop<NK, false>(a, pr, l, p, n, alpha, fo, x, y);
+  if constexpr (F_PACKED) {
+    if (pr.narrow)
+      mac_loop<NK, true, true>(a, pr, l, p, n, alpha, fo, x, y);
+    else
+      mac_loop<NK, true, false>(a, pr, l, p, n, alpha, fo, x, y);
+  } else {
+    mac_loop<NK, false, false>(a, pr, l, p, n, alpha, fo, x, y);
+  }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     uint64_t xr = barrett128(x[k], q, pr.r_lo, pr.r_hi);
@@ -293,7 +303,10 @@ __global__ void __launch_bounds__(kThreads)
 template <int NK>
 hipError_t launch_mac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
   dim3 grid(P->n / kThreads, a.K);
-  hipLaunchKernelGGL((mac_kernel<NK>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  if (a.f_packed)
+    hipLaunchKernelGGL((mac_kernel<NK, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  else
+    hipLaunchKernelGGL((mac_kernel<NK, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
   return hipGetLastError();
 }
 
