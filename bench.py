@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baseline (for rocprofv3)")
+    ap.add_argument("--packed", action="store_true",
+                    help="with --profile-only: keys and TH-BSGS plaintexts in the packed layout")
     ap.add_argument("--batch-items", type=int, default=128, help="ragged batch size (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="Poisson serving run length (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
@@ -592,8 +594,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        time_lt(P, prm, level, th_split, "th", max(1, args.steps), 1, torch, H)
-        time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), 1, torch, H)
+        time_lt(P, prm, level, th_split, "th", max(1, args.steps), 1, torch, H, packed=args.packed)
+        time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), 1, torch, H, packed=args.packed)
         print("profile run done", flush=True)
         return
 

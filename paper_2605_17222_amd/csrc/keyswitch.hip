@@ -135,7 +135,9 @@ __device__ __forceinline__ void diag_keys(const KsArgs& a, const PrimeDev& pr, i
   const size_t lo = limb_off(l, n, PACKED, pr);
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
   for (int k = 0; k < a.nkeys; ++k) {
-    if (l >= a.K[k]) continue;
+    uint64_t* oa = a.out_a[k][k];
+    uint64_t* ob = a.out_b[k][k];
+    if (!oa || l >= a.K[k]) continue;
     const int beta = a.beta[k];
     uint64_t k0[kMaxBeta], k1[kMaxBeta];
     ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, beta, p, n);
@@ -156,8 +158,8 @@ __device__ __forceinline__ void diag_keys(const KsArgs& a, const PrimeDev& pr, i
         addv = ld_nt(a.add[k] + (size_t)l * n + p);
     }
     const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
-    a.out_a[k][k][o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
-    a.out_b[k][k][o] = barrett128(y, q, pr.r_lo, pr.r_hi);
+    oa[o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
+    ob[o] = barrett128(y, q, pr.r_lo, pr.r_hi);
   }
 }
 

@@ -116,3 +116,43 @@ def test_packed_errors(case):
     with pytest.raises(ValueError):
         H.ckks_lt_workspace_size(P, case.w.level, case.w.th_split, th_pts + [d["pts"]["th"][2]], H.CKKS_LT_TH_BSGS)
     torch.cuda.synchronize()
+
+
+def test_packed_batch_and_server(case):
+    # packed keys and plaintexts through a batch (three items sharing them) and
+    # through the server (a ring registered with packed keys): every result
+    # equals the single unpacked evaluation
+    import torch
+    w = case.w
+    prm = w.params
+    P = gpu_params(prm)
+    d = case.device()
+    ref = _run(case, "th", False, False)
+    keys_p = {r: H.ckks_pack(P, k) for r, k in d["keys"].items()}
+    pts_p = [None if f is None else H.ckks_pack(P, f) for f in d["pts"]["th"]]
+    c0, c1 = d["ct"]
+    items = [H.BatchItem(w.level, case.delta, c0, c1, w.th_split, pts_p, case.delta, keys_p,
+                         H.empty((w.level, prm.n)), H.empty((w.level, prm.n))) for _ in range(3)]
+    wsb = H.ckks_lt_batch_workspace_size(P, items, H.CKKS_LT_TH_BSGS)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
+    log("packed batch of 3, workspace", wsb)
+    assert H.ckks_lt_eval_batch(P, items, H.CKKS_LT_TH_BSGS, ws, wsb) == H.CKKS_OK
+    torch.cuda.synchronize()
+    for it in items:
+        assert it.status == H.CKKS_OK
+        assert np.array_equal(np.stack([H.to_host(it.out0), H.to_host(it.out1)]), ref)
+    del ws
+    outs, ids = [], []
+    with H.Server(8 << 30, max_batch=4, max_inflight=2) as S:
+        ring = H.ckks_server_add_ring(S, P, keys_p)
+        for _ in range(4):
+            o0, o1 = H.empty((w.level, prm.n)), H.empty((w.level, prm.n))
+            ids.append(H.ckks_server_submit(S, ring, w.level, case.delta, c0, c1, w.th_split, pts_p, case.delta,
+                                            o0, o1))
+            outs.append((o0, o1))
+        H.ckks_server_wait_all(S)
+        for i in ids:
+            status, _ = H.ckks_server_poll(S, i)
+            assert status == H.CKKS_OK, H.strerror(status)
+    for o0, o1 in outs:
+        assert np.array_equal(np.stack([H.to_host(o0), H.to_host(o1)]), ref)

@@ -63,6 +63,17 @@ def test_params_create_rejects_bad_input_without_gpu():
         H.ckks_params_create(11, prm.q, prm.p, 3)  # ring below the supported range
 
 
+def test_pack_rejects_bad_input_without_gpu():
+    # ckks_pack and ckks_packed_poly_bytes check their arguments first.
+    import ctypes
+    import paper_2605_17222_amd as H
+    _lib_path()
+    L = H.lib()
+    size = ctypes.c_size_t()
+    assert L.ckks_packed_poly_bytes(None, ctypes.byref(size)) == H.CKKS_E_INVALID_ARG
+    assert L.ckks_pack(None, 1, None, None, None) == H.CKKS_E_INVALID_ARG
+
+
 def test_modarith_host_exact(tmp_path):
     src = os.path.join(ROOT, "tests", "native", "modarith_host_test.cpp")
     exe = str(tmp_path / "mah")
