@@ -40,12 +40,12 @@ __device__ __forceinline__ size_t poly_stride(bool packed, uint64_t pk_bytes, in
   return packed ? pk_bytes : (size_t)kmax * n * 8;
 }
 
-// Key k's limb l of polynomials (2 b, 2 b + 1), b < kbeta, at position p.
-template <bool NARROW>
-__device__ __forceinline__ void ld_key(uint64_t (&k0)[kMaxBeta], uint64_t (&k1)[kMaxBeta], const uint8_t* base,
-                                       size_t stride, int kbeta, size_t p, size_t n) {
+// Key k's limb l of polynomials (2 b, 2 b + 1), b < kbeta <= MB, at position p.
+template <bool NARROW, int MB>
+__device__ __forceinline__ void ld_key(uint64_t (&k0)[MB], uint64_t (&k1)[MB], const uint8_t* base, size_t stride,
+                                       int kbeta, size_t p, size_t n) {
 #pragma unroll
-  for (int b = 0; b < kMaxBeta; ++b) {
+  for (int b = 0; b < MB; ++b) {
     if (b < kbeta) {
       k0[b] = ld_word<NARROW>(base + (2 * b) * stride, p, n);
       k1[b] = ld_word<NARROW>(base + (2 * b + 1) * stride, p, n);
@@ -54,16 +54,18 @@ __device__ __forceinline__ void ld_key(uint64_t (&k0)[kMaxBeta], uint64_t (&k1)[
 }
 
 // The keys of a key-switch launch against the digits d (limb l, position p):
-// key k's product with digit set i is written at phi_k's position of p.
-template <int NDIG, bool PACKED, bool NARROW>
+// key k's product with digit set i is written at phi_k's position of p.  MB
+// is the launch's largest digit count (kbeta), which sizes the register
+// arrays: fewer registers at the common digit counts, higher occupancy.
+template <int NDIG, int MB, bool PACKED, bool NARROW>
 __device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n, int log_n,
-                                        const uint64_t (&d)[NDIG][kMaxBeta], const uint64_t (&addv)[NDIG]) {
+                                        const uint64_t (&d)[NDIG][MB], const uint64_t (&addv)[NDIG]) {
   const uint64_t q = pr.q;
   const size_t lo = limb_off(l, n, PACKED, pr);
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
   for (int k = 0; k < a.nkeys; ++k) {
-    uint64_t k0[kMaxBeta], k1[kMaxBeta];
-    ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.kbeta, p, n);
+    uint64_t k0[MB], k1[MB];
+    ld_key<NARROW, MB>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.kbeta, p, n);
     const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
 #pragma unroll
     for (int i = 0; i < NDIG; ++i) {
@@ -72,7 +74,7 @@ __device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int
       uint64_t* ob = a.out_b[i][k];
       U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
-      for (int b = 0; b < kMaxBeta; ++b) {
+      for (int b = 0; b < MB; ++b) {
         if (b < a.beta[i]) {
           add128(x, mul_wide(d[i][b], k0[b]));
           add128(y, mul_wide(d[i][b], k1[b]));
@@ -86,7 +88,7 @@ __device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int
 
 // PACKED: every key of the launch is stored packed.  Limb l is uniform over a
 // block, so the narrow/wide choice is made once, outside the key loop.
-template <int NDIG, bool PACKED>
+template <int NDIG, int MB, bool PACKED>
 __global__ void __launch_bounds__(kThreads)
     ks_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
@@ -95,13 +97,13 @@ __global__ void __launch_bounds__(kThreads)
   const PrimeDev& pr = primes[l];
   const uint64_t q = pr.q;
 
-  uint64_t d[NDIG][kMaxBeta], addv[NDIG];
+  uint64_t d[NDIG][MB], addv[NDIG];
 #pragma unroll
   for (int i = 0; i < NDIG; ++i) {
     addv[i] = 0;
     if (l >= a.K[i]) continue;  // this digit set's level has fewer limbs
 #pragma unroll
-    for (int b = 0; b < kMaxBeta; ++b)
+    for (int b = 0; b < MB; ++b)
       if (b < a.beta[i]) d[i][b] = ld_nt(a.digits[i] + ((size_t)b * a.K[i] + l) * n + p);
     if (a.add[i]) {
       if (a.add_pscaled[i])
@@ -112,22 +114,34 @@ __global__ void __launch_bounds__(kThreads)
   }
   if constexpr (PACKED) {
     if (pr.narrow)
-      ks_keys<NDIG, true, true>(a, pr, l, p, n, log_n, d, addv);
+      ks_keys<NDIG, MB, true, true>(a, pr, l, p, n, log_n, d, addv);
     else
-      ks_keys<NDIG, true, false>(a, pr, l, p, n, log_n, d, addv);
+      ks_keys<NDIG, MB, true, false>(a, pr, l, p, n, log_n, d, addv);
   } else {
-    ks_keys<NDIG, false, false>(a, pr, l, p, n, log_n, d, addv);
+    ks_keys<NDIG, MB, false, false>(a, pr, l, p, n, log_n, d, addv);
   }
+}
+
+template <int NDIG, int MB>
+hipError_t launch_ks_mb(const ckks_params* P, const KsArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.maxK);
+  if (a.key_packed)
+    hipLaunchKernelGGL((ks_kernel<NDIG, MB, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  else
+    hipLaunchKernelGGL((ks_kernel<NDIG, MB, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  return hipGetLastError();
 }
 
 template <int NDIG>
 hipError_t launch_ks(const ckks_params* P, const KsArgs& a, hipStream_t s) {
-  dim3 grid(P->n / kThreads, a.maxK);
-  if (a.key_packed)
-    hipLaunchKernelGGL((ks_kernel<NDIG, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
-  else
-    hipLaunchKernelGGL((ks_kernel<NDIG, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
-  return hipGetLastError();
+  static_assert(kMaxBeta == 4, "one instantiation per digit count");
+  switch (a.kbeta) {
+    case 1: return launch_ks_mb<NDIG, 1>(P, a, s);
+    case 2: return launch_ks_mb<NDIG, 2>(P, a, s);
+    case 3: return launch_ks_mb<NDIG, 3>(P, a, s);
+    case 4: return launch_ks_mb<NDIG, 4>(P, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // One-to-one launches (key k with digit set k only, as in the separate
@@ -145,7 +159,7 @@ __device__ __forceinline__ void diag_keys(const KsArgs& a, const PrimeDev& pr, i
     if (!oa || l >= a.K[k]) continue;
     const int beta = a.beta[k];
     uint64_t k0[kMaxBeta], k1[kMaxBeta];
-    ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, beta, p, n);
+    ld_key<NARROW, kMaxBeta>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, beta, p, n);
     U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
     for (int b = 0; b < kMaxBeta; ++b) {
@@ -196,7 +210,7 @@ __device__ __forceinline__ void gather_keys(const KsGatherArgs& a, const PrimeDe
     const uint32_t src = auto_index(p, a.gal[k], log_n);
     const size_t s = (size_t)l * n + src;
     uint64_t k0[kMaxBeta], k1[kMaxBeta];
-    ld_key<NARROW>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.beta, src, n);
+    ld_key<NARROW, kMaxBeta>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.beta, src, n);
     const uint64_t* __restrict__ dg = a.digits[k];
     U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
