@@ -570,7 +570,7 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024, onfly=Fa
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
