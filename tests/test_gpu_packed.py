@@ -119,9 +119,10 @@ def test_packed_errors(case):
 
 
 def test_packed_batch_and_server(case):
-    # packed keys and plaintexts through a batch (three items sharing them) and
-    # through the server (a ring registered with packed keys): every result
-    # equals the single unpacked evaluation
+    # packed keys and plaintexts through a batch (packed and unpacked items
+    # mixed, so packed and unpacked keys meet in the same phase) and through
+    # the server (a ring registered with packed keys): every result equals the
+    # single unpacked evaluation
     import torch
     w = case.w
     prm = w.params
@@ -131,11 +132,12 @@ def test_packed_batch_and_server(case):
     keys_p = {r: H.ckks_pack(P, k) for r, k in d["keys"].items()}
     pts_p = [None if f is None else H.ckks_pack(P, f) for f in d["pts"]["th"]]
     c0, c1 = d["ct"]
-    items = [H.BatchItem(w.level, case.delta, c0, c1, w.th_split, pts_p, case.delta, keys_p,
-                         H.empty((w.level, prm.n)), H.empty((w.level, prm.n))) for _ in range(3)]
+    forms = [(pts_p, keys_p), (d["pts"]["th"], d["keys"]), (pts_p, keys_p), (d["pts"]["th"], keys_p)]
+    items = [H.BatchItem(w.level, case.delta, c0, c1, w.th_split, pts, case.delta, keys,
+                         H.empty((w.level, prm.n)), H.empty((w.level, prm.n))) for pts, keys in forms]
     wsb = H.ckks_lt_batch_workspace_size(P, items, H.CKKS_LT_TH_BSGS)
     ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
-    log("packed batch of 3, workspace", wsb)
+    log("mixed packed/unpacked batch of 4, workspace", wsb)
     assert H.ckks_lt_eval_batch(P, items, H.CKKS_LT_TH_BSGS, ws, wsb) == H.CKKS_OK
     torch.cuda.synchronize()
     for it in items:
