@@ -606,7 +606,7 @@ def main():
     dom = max(prof, key=lambda k: prof[k][1])
     dom_id = H.KERNELS.index(dom)
     # 2) the timed region: K steps, HIP events around the dominant kernel only
-    wall, ms_ev, prof_dom, _ = time_lt(P, prm, level, th_split, "th", args.steps, 1, torch, H, 1 << dom_id)
+    wall, ms_ev, prof_dom, _ = time_lt(P, prm, level, th_split, "th", args.steps, args.warmup, torch, H, 1 << dom_id)
     ms_step = ms_ev / args.steps
     lt_s = args.steps / wall
     # 3) plain BSGS beside it
