@@ -529,7 +529,9 @@ def ckks_pack(params: Params, polys, stream=None) -> Packed:
     key [beta_max, 2, kmax, N] or a plaintext [kmax, N]) into a new Packed."""
     import torch
     kmax = params.alpha + params.max_level + 1
-    assert polys.is_contiguous() and polys.shape[-2:] == (kmax, params.n)
+    if not polys.is_contiguous() or tuple(polys.shape[-2:]) != (kmax, params.n):
+        raise ValueError("ckks_pack: need a contiguous [..., %d, %d] tensor, got %s" % (kmax, params.n,
+                                                                                      tuple(polys.shape)))
     count = polys.numel() // (kmax * params.n)
     out = torch.empty(count * ckks_packed_poly_bytes(params), dtype=torch.uint8, device=polys.device)
     _check(lib().ckks_pack(params, count, _ptr(polys), _ptr(out), _stream(stream)), "ckks_pack")
@@ -610,7 +612,8 @@ def to_device(a, device="cuda"):
     import numpy as np
     import torch
     a = np.ascontiguousarray(a)
-    assert a.dtype == np.uint64
+    if a.dtype != np.uint64:
+        raise TypeError("to_device: need uint64 words, got %s" % a.dtype)
     return torch.from_numpy(a.view(np.int64)).to(device)
 
 
