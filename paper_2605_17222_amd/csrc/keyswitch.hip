@@ -63,9 +63,13 @@ __device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int
   const uint64_t q = pr.q;
   const size_t lo = limb_off(l, n, PACKED, pr);
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
+  // key k + 1 is loaded while key k's products are formed (the stores that
+  // follow do not delay those loads)
+  uint64_t k0[MB], k1[MB], n0[MB], n1[MB];
+  ld_key<NARROW, MB>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[0]) + lo, stride, a.kbeta, p, n);
   for (int k = 0; k < a.nkeys; ++k) {
-    uint64_t k0[MB], k1[MB];
-    ld_key<NARROW, MB>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.kbeta, p, n);
+    if (k + 1 < a.nkeys)
+      ld_key<NARROW, MB>(n0, n1, reinterpret_cast<const uint8_t*>(a.key[k + 1]) + lo, stride, a.kbeta, p, n);
     const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
 #pragma unroll
     for (int i = 0; i < NDIG; ++i) {
@@ -82,6 +86,11 @@ __device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int
       }
       __builtin_nontemporal_store(add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv[i], q), oa + o);
       __builtin_nontemporal_store(barrett128(y, q, pr.r_lo, pr.r_hi), ob + o);
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      k0[b] = n0[b];
+      k1[b] = n1[b];
     }
   }
 }
