@@ -155,43 +155,66 @@ hipError_t launch_ks(const ckks_params* P, const KsArgs& a, hipStream_t s) {
 
 // One-to-one launches (key k with digit set k only, as in the separate
 // giant-step rotations of plain BSGS): each key's digits are loaded inside
-// the key loop, so only one digit set is live and occupancy stays high.
-template <bool PACKED, bool NARROW>
+// the key loop, so only one digit set is live and occupancy stays high.  The
+// operands of key k + 1 are loaded while key k's products are formed.
+template <int MB>
+struct DiagOps {
+  uint64_t k0[MB], k1[MB], d[MB], add;
+};
+
+template <bool NARROW, int MB>
+__device__ __forceinline__ void diag_load(DiagOps<MB>& o, const KsArgs& a, int k, int l, uint32_t p, size_t n,
+                                          size_t lo, size_t stride, int alpha) {
+  const int beta = a.beta[k];
+  ld_key<NARROW, MB>(o.k0, o.k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, beta, p, n);
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+    if (b < beta) o.d[b] = ld_nt(a.digits[k] + ((size_t)b * a.K[k] + l) * n + p);
+  o.add = 0;
+  if (a.add[k]) {
+    if (a.add_pscaled[k])
+      o.add = (l < alpha) ? 0 : ld_nt(a.add[k] + (size_t)(l - alpha) * n + p);
+    else
+      o.add = ld_nt(a.add[k] + (size_t)l * n + p);
+  }
+}
+
+template <bool PACKED, bool NARROW, int MB>
 __device__ __forceinline__ void diag_keys(const KsArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n, int log_n,
                                           int alpha) {
   const uint64_t q = pr.q;
   const size_t lo = limb_off(l, n, PACKED, pr);
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
-  for (int k = 0; k < a.nkeys; ++k) {
-    uint64_t* oa = a.out_a[k][k];
-    uint64_t* ob = a.out_b[k][k];
-    if (!oa || l >= a.K[k]) continue;
+  // keys whose digit set has fewer limbs than l are skipped
+  int k = 0;
+  while (k < a.nkeys && (!a.out_a[k][k] || l >= a.K[k])) ++k;
+  if (k == a.nkeys) return;
+  DiagOps<MB> cur, nxt;
+  diag_load<NARROW, MB>(cur, a, k, l, p, n, lo, stride, alpha);
+  while (k < a.nkeys) {
+    int k2 = k + 1;
+    while (k2 < a.nkeys && (!a.out_a[k2][k2] || l >= a.K[k2])) ++k2;
+    if (k2 < a.nkeys) diag_load<NARROW, MB>(nxt, a, k2, l, p, n, lo, stride, alpha);
     const int beta = a.beta[k];
-    uint64_t k0[kMaxBeta], k1[kMaxBeta];
-    ld_key<NARROW, kMaxBeta>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, beta, p, n);
     U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
-    for (int b = 0; b < kMaxBeta; ++b) {
+    for (int b = 0; b < MB; ++b) {
       if (b < beta) {
-        const uint64_t d = ld_nt(a.digits[k] + ((size_t)b * a.K[k] + l) * n + p);
-        add128(x, mul_wide(d, k0[b]));
-        add128(y, mul_wide(d, k1[b]));
+        add128(x, mul_wide(cur.d[b], cur.k0[b]));
+        add128(y, mul_wide(cur.d[b], cur.k1[b]));
       }
     }
-    uint64_t addv = 0;
-    if (a.add[k]) {
-      if (a.add_pscaled[k])
-        addv = (l < alpha) ? 0 : shoup(ld_nt(a.add[k] + (size_t)(l - alpha) * n + p), pr.pmod, pr.pmod_sh, q);
-      else
-        addv = ld_nt(a.add[k] + (size_t)l * n + p);
-    }
+    uint64_t addv = cur.add;
+    if (a.add[k] && a.add_pscaled[k] && l >= alpha) addv = shoup(addv, pr.pmod, pr.pmod_sh, q);
     const size_t o = (size_t)l * n + auto_index(p, a.gal_inv[k], log_n);
-    oa[o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
-    ob[o] = barrett128(y, q, pr.r_lo, pr.r_hi);
+    a.out_a[k][k][o] = add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), addv, q);
+    a.out_b[k][k][o] = barrett128(y, q, pr.r_lo, pr.r_hi);
+    cur = nxt;
+    k = k2;
   }
 }
 
-template <bool PACKED>
+template <bool PACKED, int MB>
 __global__ void __launch_bounds__(kThreads)
     ks_diag_kernel(KsArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const size_t n = (size_t)1 << log_n;
@@ -200,42 +223,70 @@ __global__ void __launch_bounds__(kThreads)
   const PrimeDev& pr = primes[l];
   if constexpr (PACKED) {
     if (pr.narrow)
-      diag_keys<true, true>(a, pr, l, p, n, log_n, alpha);
+      diag_keys<true, true, MB>(a, pr, l, p, n, log_n, alpha);
     else
-      diag_keys<true, false>(a, pr, l, p, n, log_n, alpha);
+      diag_keys<true, false, MB>(a, pr, l, p, n, log_n, alpha);
   } else {
-    diag_keys<false, false>(a, pr, l, p, n, log_n, alpha);
+    diag_keys<false, false, MB>(a, pr, l, p, n, log_n, alpha);
   }
 }
 
-// The gather's key loop (limb l, output position p).
-template <bool PACKED, bool NARROW>
+template <int MB>
+hipError_t launch_diag_mb(const ckks_params* P, const KsArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.maxK);
+  if (a.key_packed)
+    hipLaunchKernelGGL((ks_diag_kernel<true, MB>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  else
+    hipLaunchKernelGGL((ks_diag_kernel<false, MB>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
+  return hipGetLastError();
+}
+
+// The gather's key loop (limb l, output position p): the operands of key
+// k + 1 (its limbs, digits and u0 at its source position) are loaded while
+// key k's products are formed.
+template <int MB>
+struct GatherOps {
+  uint64_t k0[MB], k1[MB], d[MB], add;
+};
+
+template <bool NARROW, int MB>
+__device__ __forceinline__ void gather_load(GatherOps<MB>& o, const KsGatherArgs& a, int k, int l, uint32_t p,
+                                            size_t n, int log_n, size_t lo, size_t stride) {
+  const uint32_t src = auto_index(p, a.gal[k], log_n);
+  const size_t s = (size_t)l * n + src;
+  ld_key<NARROW, MB>(o.k0, o.k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.beta, src, n);
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+    if (b < a.beta) o.d[b] = ld_nt(a.digits[k] + (size_t)b * a.K * n + s);
+  o.add = ld_nt(a.add[k] + s);
+}
+
+template <bool PACKED, bool NARROW, int MB>
 __device__ __forceinline__ void gather_keys(const KsGatherArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n,
                                             int log_n, uint64_t& c0, uint64_t& c1) {
   const uint64_t q = pr.q;
   const size_t lo = limb_off(l, n, PACKED, pr);
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
+  if (a.nk <= 0) return;
+  GatherOps<MB> cur, nxt;
+  gather_load<NARROW, MB>(cur, a, 0, l, p, n, log_n, lo, stride);
   for (int k = 0; k < a.nk; ++k) {
-    const uint32_t src = auto_index(p, a.gal[k], log_n);
-    const size_t s = (size_t)l * n + src;
-    uint64_t k0[kMaxBeta], k1[kMaxBeta];
-    ld_key<NARROW, kMaxBeta>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[k]) + lo, stride, a.beta, src, n);
-    const uint64_t* __restrict__ dg = a.digits[k];
+    if (k + 1 < a.nk) gather_load<NARROW, MB>(nxt, a, k + 1, l, p, n, log_n, lo, stride);
     U128 x = {0, 0}, y = {0, 0};
 #pragma unroll
-    for (int b = 0; b < kMaxBeta; ++b) {
+    for (int b = 0; b < MB; ++b) {
       if (b < a.beta) {
-        const uint64_t d = ld_nt(dg + (size_t)b * a.K * n + s);
-        add128(x, mul_wide(d, k0[b]));
-        add128(y, mul_wide(d, k1[b]));
+        add128(x, mul_wide(cur.d[b], cur.k0[b]));
+        add128(y, mul_wide(cur.d[b], cur.k1[b]));
       }
     }
-    c0 = add_mod(c0, add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), ld_nt(a.add[k] + s), q), q);
+    c0 = add_mod(c0, add_mod(barrett128(x, q, pr.r_lo, pr.r_hi), cur.add, q), q);
     c1 = add_mod(c1, barrett128(y, q, pr.r_lo, pr.r_hi), q);
+    cur = nxt;
   }
 }
 
-template <bool PACKED>
+template <bool PACKED, int MB>
 __global__ void __launch_bounds__(kThreads)
     ks_gather_kernel(KsGatherArgs a, const PrimeDev* __restrict__ primes, int log_n) {
   const size_t n = (size_t)1 << log_n;
@@ -246,14 +297,24 @@ __global__ void __launch_bounds__(kThreads)
   uint64_t c0 = a.c0[o], c1 = a.c1[o];
   if constexpr (PACKED) {
     if (pr.narrow)
-      gather_keys<true, true>(a, pr, l, p, n, log_n, c0, c1);
+      gather_keys<true, true, MB>(a, pr, l, p, n, log_n, c0, c1);
     else
-      gather_keys<true, false>(a, pr, l, p, n, log_n, c0, c1);
+      gather_keys<true, false, MB>(a, pr, l, p, n, log_n, c0, c1);
   } else {
-    gather_keys<false, false>(a, pr, l, p, n, log_n, c0, c1);
+    gather_keys<false, false, MB>(a, pr, l, p, n, log_n, c0, c1);
   }
   a.c0[o] = c0;
   a.c1[o] = c1;
+}
+
+template <int MB>
+hipError_t launch_gather_mb(const ckks_params* P, const KsGatherArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  if (a.key_packed)
+    hipLaunchKernelGGL((ks_gather_kernel<true, MB>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  else
+    hipLaunchKernelGGL((ks_gather_kernel<false, MB>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  return hipGetLastError();
 }
 
 // The m-outer loop of the MAC for one limb: (a_m, b_m) and the NK plaintexts
@@ -374,12 +435,13 @@ hipError_t launch_keyswitch(const ckks_params* P, const KsArgs& a, hipStream_t s
   for (int k = 0; k < a.nkeys; ++k) key_bytes += 2.0 * a.kbeta * limb_bytes(P, a.maxK, a.key_packed);
   ProfScope prof(CKKS_KERNEL_KEYSWITCH, s, words * P->n * 8 + key_bytes);
   if (a.diag) {
-    dim3 grid(P->n / kThreads, a.maxK);
-    if (a.key_packed)
-      hipLaunchKernelGGL(ks_diag_kernel<true>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
-    else
-      hipLaunchKernelGGL(ks_diag_kernel<false>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha);
-    return hipGetLastError();
+    switch (a.kbeta) {
+      case 1: return launch_diag_mb<1>(P, a, s);
+      case 2: return launch_diag_mb<2>(P, a, s);
+      case 3: return launch_diag_mb<3>(P, a, s);
+      case 4: return launch_diag_mb<4>(P, a, s);
+      default: return hipErrorInvalidValue;
+    }
   }
   switch (a.ndig) {
     case 1: return launch_ks<1>(P, a, s);
@@ -398,12 +460,13 @@ hipError_t launch_keyswitch_gather(const ckks_params* P, const KsGatherArgs& a, 
   double bytes = (double)a.K * P->n * (4.0 + a.nk * (a.beta + 1)) * 8;
   bytes += a.nk * 2.0 * a.beta * limb_bytes(P, a.K, a.key_packed);
   ProfScope prof(CKKS_KERNEL_KEYSWITCH_GATHER, s, bytes);
-  dim3 grid(P->n / kThreads, a.K);
-  if (a.key_packed)
-    hipLaunchKernelGGL(ks_gather_kernel<true>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
-  else
-    hipLaunchKernelGGL(ks_gather_kernel<false>, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
-  return hipGetLastError();
+  switch (a.beta) {
+    case 1: return launch_gather_mb<1>(P, a, s);
+    case 2: return launch_gather_mb<2>(P, a, s);
+    case 3: return launch_gather_mb<3>(P, a, s);
+    case 4: return launch_gather_mb<4>(P, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_ptmac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
