@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # kernel (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see profiles/.  None once the
 # kernel has changed since the counters were taken.
 TRAFFIC = {
-    # mac_kernel<4, false> at N=2^16, level 24, TH-BSGS (4,4,4): (2 x 831093.3 + 139264.0) KiB
-    "ptmac": (2 * 831093.3 + 139264.0) * 1024,
+    # mac_kernel<4, false> at N=2^16, level 24, TH-BSGS (4,4,4): (2 x 831079.9 + 139264.0) KiB
+    "ptmac": (2 * 831079.9 + 139264.0) * 1024,
 }
 
 
@@ -44,7 +44,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50,
+                    help="untimed steps before each timed single-LT leg (the device's clocks ramp up over the "
+                         "first 10-20 steps after an idle gap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baseline (for rocprofv3)")
     ap.add_argument("--packed", action="store_true",
@@ -129,7 +131,7 @@ def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True, packe
     return c0, c1, keys, pts
 
 
-def step_percentiles(P, prm, level, split, reps, torch, H):
+def step_percentiles(P, prm, level, split, reps, torch, H, warmup=50):
     """Each of `reps` steps bracketed by its own HIP events: p10/p50/p90 ms."""
     c0, c1, keys, pts = make_inputs(P, prm, level, split, "th", 1234, torch, H)
     code = H.CKKS_LT_TH_BSGS
@@ -139,7 +141,7 @@ def step_percentiles(P, prm, level, split, reps, torch, H):
     delta = 2.0 ** prm.log_delta
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for _ in range(3):
+    for _ in range(warmup):
         H.ckks_lt_eval(P, level, delta, c0, c1, split, pts, delta, keys, code, out0, out1, ws, ws_bytes, stream)
     torch.cuda.synchronize()
     for a, b in ev:
@@ -594,8 +596,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        time_lt(P, prm, level, th_split, "th", max(1, args.steps), 1, torch, H, packed=args.packed)
-        time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), 1, torch, H, packed=args.packed)
+        time_lt(P, prm, level, th_split, "th", max(1, args.steps), args.warmup, torch, H, packed=args.packed)
+        time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), args.warmup, torch, H, packed=args.packed)
         print("profile run done", flush=True)
         return
 
@@ -611,7 +613,7 @@ def main():
     lt_s = args.steps / wall
     # 3) plain BSGS beside it
     bs_steps = max(3, args.steps // 2)
-    wall_b, ms_ev_b, _, _ = time_lt(P, prm, level, bs_split, "bsgs", bs_steps, 2, torch, H)
+    wall_b, ms_ev_b, _, _ = time_lt(P, prm, level, bs_split, "bsgs", bs_steps, args.warmup, torch, H)
     bs_ms = ms_ev_b / bs_steps
 
     n_l, ms_l, bytes_l = prof_dom[dom]
@@ -652,12 +654,12 @@ def main():
         "roofline": roofline,
         "valu": valu,
         "kernels": breakdown,
-        "step_ms": step_percentiles(P, prm, level, th_split, 100, torch, H),
+        "step_ms": step_percentiles(P, prm, level, th_split, 100, torch, H, args.warmup),
     }
     # the split the library's autotuner picks for this workload, timed the same way
     at_split, at_pred = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, 64)
     at_split = tuple(at_split)
-    wall_a, ms_a, _, _ = time_lt(P, prm, level, at_split, "th", args.steps, 2, torch, H)
+    wall_a, ms_a, _, _ = time_lt(P, prm, level, at_split, "th", args.steps, args.warmup, torch, H)
     out["autotuned_split"] = {"split": list(at_split), "predicted_ms": round(at_pred * 1e3, 4),
                               "ms_per_lt": round(ms_a / args.steps, 4), "lt_per_s": round(args.steps / wall_a, 2),
                               "compulsory_bytes_per_lt": compulsory_bytes(prm, level, at_split, "th")}
@@ -666,7 +668,7 @@ def main():
     # identical results, fewer bytes for the key-switch and MAC kernels
     packed = {}
     for name, split, algo in (("th", th_split, "th"), ("th_autotuned", at_split, "th"), ("plain_bsgs", bs_split, "bsgs")):
-        wall_p, ms_p, _, _ = time_lt(P, prm, level, split, algo, args.steps, 2, torch, H, packed=True)
+        wall_p, ms_p, _, _ = time_lt(P, prm, level, split, algo, args.steps, args.warmup, torch, H, packed=True)
         packed[name] = {"split": list(split), "ms_per_lt": round(ms_p / args.steps, 4),
                         "lt_per_s": round(args.steps / wall_p, 2)}
     packed["packed_poly_bytes"] = H.ckks_packed_poly_bytes(P)
@@ -686,7 +688,7 @@ def main():
     # the same workload with its 64 plaintexts encoded on the fly, and the
     # dense n = N/2 LT (every diagonal present) that on-the-fly encoding makes
     # fit on one device, at the largest parameter set's TH split (32, 32, 32)
-    out["onfly_banded64"] = onfly_leg(P, prm, level, th_split, 64, args.steps, 2, torch, H)
+    out["onfly_banded64"] = onfly_leg(P, prm, level, th_split, 64, args.steps, args.warmup, torch, H)
     print("on-the-fly banded leg done", flush=True, file=sys.stderr)
     if args.dense_steps > 0:
         out["onfly_dense"] = onfly_leg(P, prm, level, (32, 32, 32), prm.slots, args.dense_steps, 1, torch, H)
