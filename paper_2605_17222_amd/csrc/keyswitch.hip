@@ -65,7 +65,7 @@ __device__ __forceinline__ void ks_keys(const KsArgs& a, const PrimeDev& pr, int
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
   // key k + 1 is loaded while key k's products are formed (the stores that
   // follow do not delay those loads)
-  uint64_t k0[MB], k1[MB], n0[MB], n1[MB];
+  uint64_t k0[MB] = {}, k1[MB] = {}, n0[MB] = {}, n1[MB] = {};
   ld_key<NARROW, MB>(k0, k1, reinterpret_cast<const uint8_t*>(a.key[0]) + lo, stride, a.kbeta, p, n);
   for (int k = 0; k < a.nkeys; ++k) {
     if (k + 1 < a.nkeys)
@@ -189,7 +189,7 @@ __device__ __forceinline__ void diag_keys(const KsArgs& a, const PrimeDev& pr, i
   int k = 0;
   while (k < a.nkeys && (!a.out_a[k][k] || l >= a.K[k])) ++k;
   if (k == a.nkeys) return;
-  DiagOps<MB> cur, nxt;
+  DiagOps<MB> cur{}, nxt{};
   diag_load<NARROW, MB>(cur, a, k, l, p, n, lo, stride, alpha);
   while (k < a.nkeys) {
     int k2 = k + 1;
@@ -268,7 +268,7 @@ __device__ __forceinline__ void gather_keys(const KsGatherArgs& a, const PrimeDe
   const size_t lo = limb_off(l, n, PACKED, pr);
   const size_t stride = poly_stride(PACKED, a.pk_poly_bytes, a.kmax, n);
   if (a.nk <= 0) return;
-  GatherOps<MB> cur, nxt;
+  GatherOps<MB> cur{}, nxt{};
   gather_load<NARROW, MB>(cur, a, 0, l, p, n, log_n, lo, stride);
   for (int k = 0; k < a.nk; ++k) {
     if (k + 1 < a.nk) gather_load<NARROW, MB>(nxt, a, k + 1, l, p, n, log_n, lo, stride);
