@@ -317,13 +317,74 @@ hipError_t launch_gather_mb(const ckks_params* P, const KsGatherArgs& a, hipStre
   return hipGetLastError();
 }
 
+template <int NK>
+struct MacOps {
+  uint64_t a, b, f[NK];
+};
+
+// Index m's operands: (a_m, b_m) (for m = 0 with P c', the raw c' words) and
+// the NK plaintext words (0 where a plaintext is absent).
+template <int NK, bool PACKED, bool NARROW, typename PrimeT>
+__device__ __forceinline__ void mac_load(MacOps<NK>& o, const MacArgs& a, const PrimeT& pr, int m, int l, size_t p,
+                                         size_t n, int alpha, size_t fo) {
+  const size_t off = (size_t)l * n + p;
+  if (m == 0 && a.pscaled0) {
+    const int lq = l + a.prime_off - alpha;
+    o.a = lq < 0 ? 0 : ld_nt(a.a[0] + (size_t)lq * n + p);
+    o.b = lq < 0 ? 0 : ld_nt(a.b[0] + (size_t)lq * n + p);
+  } else {
+    o.a = ld_nt(a.a[m] + off);
+    o.b = ld_nt(a.b[m] + off);
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const uint64_t* __restrict__ fp = a.f[k][m];
+    o.f[k] = 0;
+    if (fp) {
+      if constexpr (PACKED)
+        o.f[k] = ld_word<NARROW>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n);
+      else
+        o.f[k] = ld_nt(fp + off);  // the word offset the (a_m, b_m) loads use
+    }
+  }
+}
+
 // The m-outer loop of the MAC for one limb: (a_m, b_m) and the NK plaintexts
-// of index m are loaded together and folded into NK pairs of 128-bit
-// accumulators, so few values are live and many loads are in flight per
-// wavefront.  fo: byte offset of the limb within each plaintext.
+// of index m are folded into NK pairs of 128-bit accumulators while the
+// operands of m + 1 are loaded, so few values are live and loads stay in
+// flight across iterations.  fo: byte offset of the limb within each
+// plaintext.
 template <int NK, bool PACKED, bool NARROW, typename PrimeT>
 __device__ __forceinline__ void mac_loop(const MacArgs& a, const PrimeT& pr, int l, size_t p, size_t n, int alpha,
                                          size_t fo, U128 (&x)[NK], U128 (&y)[NK]) {
+  const uint64_t q = pr.q;
+  if (a.nm <= 0) return;
+  MacOps<NK> cur{}, nxt{};
+  mac_load<NK, PACKED, NARROW>(cur, a, pr, 0, l, p, n, alpha, fo);
+  for (int m = 0; m < a.nm; ++m) {
+    if (m + 1 < a.nm) mac_load<NK, PACKED, NARROW>(nxt, a, pr, m + 1, l, p, n, alpha, fo);
+    uint64_t av = cur.a, bv = cur.b;
+    if (m == 0 && a.pscaled0) {
+      // (a_0, b_0) = (P c0', P c1'): zero on the special primes.
+      av = shoup(av, pr.pmod, pr.pmod_sh, q);
+      bv = shoup(bv, pr.pmod, pr.pmod_sh, q);
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      if (a.f[k][m]) {
+        add128(x[k], mul_wide(av, cur.f[k]));
+        add128(y[k], mul_wide(bv, cur.f[k]));
+      }
+    }
+    if (m + 1 < a.nm) cur = nxt;
+  }
+}
+
+// The MAC loop for packed plaintexts: two iterations unrolled (the packed
+// loads take more registers, and a pipelined loop would cost a wave).
+template <int NK, bool NARROW, typename PrimeT>
+__device__ __forceinline__ void mac_loop_packed(const MacArgs& a, const PrimeT& pr, int l, size_t p, size_t n,
+                                                int alpha, size_t fo, U128 (&x)[NK], U128 (&y)[NK]) {
   const uint64_t q = pr.q;
   const size_t off = (size_t)l * n + p;
 #pragma unroll 2
@@ -342,11 +403,7 @@ __device__ __forceinline__ void mac_loop(const MacArgs& a, const PrimeT& pr, int
     for (int k = 0; k < NK; ++k) {
       const uint64_t* __restrict__ fp = a.f[k][m];
       if (fp) {
-        uint64_t f;
-        if constexpr (PACKED)
-          f = ld_word<NARROW>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n);
-        else
-          f = ld_nt(fp + off);  // the word offset the (a_m, b_m) loads use
+        const uint64_t f = ld_word<NARROW>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n);
         add128(x[k], mul_wide(av, f));
         add128(y[k], mul_wide(bv, f));
       }
@@ -372,9 +429,9 @@ __global__ void __launch_bounds__(kThreads)
   for (int k = 0; k < NK; ++k) x[k] = y[k] = U128{0, 0};
   if constexpr (F_PACKED) {
     if (pr.narrow)
-      mac_loop<NK, true, true>(a, pr, l, p, n, alpha, fo, x, y);
+      mac_loop_packed<NK, true>(a, pr, l, p, n, alpha, fo, x, y);
     else
-      mac_loop<NK, true, false>(a, pr, l, p, n, alpha, fo, x, y);
+      mac_loop_packed<NK, false>(a, pr, l, p, n, alpha, fo, x, y);
   } else {
     mac_loop<NK, false, false>(a, pr, l, p, n, alpha, fo, x, y);
   }
