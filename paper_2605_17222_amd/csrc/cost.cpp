@@ -109,11 +109,12 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
     r = *rates;
   } else {
     // Fitted on one MI355X at N = 2^16 (levels 8..24, 16..511 diagonals,
-    // 120 splits; mean prediction error 7%): BConv from its own kernel time.
-    r.ntt_limb_s = 4.19e-7;
-    r.bconv_product_s = 0.59e-12;
-    r.hbm_bytes_per_s = 4.06e12;
-    r.layer_s = 45e-6;
+    // 120 splits, 30 warm-up steps each; mean prediction error 4%): BConv
+    // from its own kernel time.
+    r.ntt_limb_s = 3.87e-7;
+    r.bconv_product_s = 0.55e-12;
+    r.hbm_bytes_per_s = 4.72e12;
+    r.layer_s = 68.7e-6;
   }
   if (algo == CKKS_LT_DH_BSGS) {  // Algorithm 2 with an empty inner layer
     n3 = n2;
