@@ -171,6 +171,18 @@ struct AutoArgs {
   uint32_t gal;         // out[p] = (in + add)[auto_index(p, gal)]
 };
 
+// Several automorphisms of nlimbs limbs in one launch (blockIdx.z = entry);
+// the entries' outputs must be distinct (they run concurrently).
+constexpr int kMaxAuto = 16;
+struct AutoBatchArgs {
+  int count, nlimbs, prime_off;
+  const uint64_t* in[kMaxAuto];
+  const uint64_t* add[kMaxAuto];  // may be null
+  uint64_t* out[kMaxAuto];
+  int accumulate[kMaxAuto];
+  uint32_t gal[kMaxAuto];
+};
+
 // Brackets one launch with HIP events when its kernel is being timed.
 class ProfScope {
  public:
@@ -209,6 +221,7 @@ hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipS
 hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGatherArgs& a, hipStream_t s);
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
 hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
+hipError_t launch_automorph_batch(const struct ::ckks_params* P, const AutoBatchArgs& a, hipStream_t s);
 hipError_t launch_encode_fft(const struct ::ckks_params* P, const EncArgs& a, hipStream_t s);
 // count full PQ polynomials [count][Kmax][N] -> packed [count][pk_poly_bytes].
 hipError_t launch_pack(const struct ::ckks_params* P, int count, const uint64_t* in, uint8_t* out, hipStream_t s);

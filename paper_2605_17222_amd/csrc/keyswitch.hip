@@ -472,6 +472,21 @@ __global__ void __launch_bounds__(kThreads)
   __builtin_nontemporal_store(v, a.out + o);
 }
 
+__global__ void __launch_bounds__(kThreads)
+    auto_batch_kernel(AutoBatchArgs a, const PrimeDev* __restrict__ primes, int log_n) {
+  const size_t n = (size_t)1 << log_n;
+  const uint32_t p = blockIdx.x * kThreads + threadIdx.x;
+  const int l = blockIdx.y;
+  const int e = blockIdx.z;
+  const uint64_t q = primes[l + a.prime_off].q;
+  const size_t s = (size_t)l * n + auto_index(p, a.gal[e], log_n);
+  uint64_t v = ld_nt(a.in[e] + s);
+  if (a.add[e]) v = add_mod(v, a.add[e][s], q);
+  const size_t o = (size_t)l * n + p;
+  if (a.accumulate[e]) v = add_mod(v, a.out[e][o], q);
+  __builtin_nontemporal_store(v, a.out[e] + o);
+}
+
 }  // namespace
 
 // Bytes of the first `count` limbs of a PQ polynomial, packed or not.
@@ -543,6 +558,17 @@ hipError_t launch_ptmac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
     case 8: return launch_mac<8>(P, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_automorph_batch(const ckks_params* P, const AutoBatchArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  if (a.count > kMaxAuto) return hipErrorInvalidValue;
+  double words = 0;
+  for (int e = 0; e < a.count; ++e) words += 2 + (a.add[e] ? 1 : 0) + (a.accumulate[e] ? 1 : 0);
+  ProfScope prof(CKKS_KERNEL_AUTOMORPH, s, words * a.nlimbs * P->n * 8);
+  dim3 grid(P->n / kThreads, a.nlimbs, a.count);
+  hipLaunchKernelGGL(auto_batch_kernel, grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  return hipGetLastError();
 }
 
 hipError_t launch_automorph(const ckks_params* P, const AutoArgs& a, hipStream_t s) {

@@ -473,12 +473,39 @@ void rotate(Run& R, int level, const std::vector<RotJob>& jobs, const KeySet& ks
     decompose(R, dc);
     keyswitch(R, tasks);
     divide(R, DIV_MODDOWN, md);
+    // the phi applications of the chunk, batched into launches whose entries
+    // do not overlap: no entry writes what another reads or writes (jobs that
+    // accumulate into one output go to consecutive launches, in order)
+    AutoBatchArgs ab;
+    memset(&ab, 0, sizeof(ab));
+    ab.nlimbs = Lq;
+    ab.prime_off = P->alpha;
+    auto flush = [&]() {
+      if (ab.count > 0 && R.live()) R.check(launch_automorph_batch(P, ab, R.s));
+      ab.count = 0;
+    };
+    auto push = [&](const uint64_t* in, const uint64_t* add, uint64_t* out, bool acc, uint32_t g) {
+      for (int e = 0; e < ab.count; ++e)
+        if (ab.out[e] == out || ab.out[e] == in || (add && ab.out[e] == add) || ab.in[e] == out ||
+            ab.add[e] == out) {
+          flush();
+          break;
+        }
+      if (ab.count == kMaxAuto) flush();
+      ab.in[ab.count] = in;
+      ab.add[ab.count] = add;
+      ab.out[ab.count] = out;
+      ab.accumulate[ab.count] = acc ? 1 : 0;
+      ab.gal[ab.count] = g;
+      ++ab.count;
+    };
     for (size_t t = 0; t < nj; ++t) {
       const RotJob& J = jobs[j0 + t];
       const uint32_t g = galois(P, J.r);
-      automorph(R, Lq, P->alpha, g, Xq[t], J.c0, J.o0, J.accumulate);
-      automorph(R, Lq, P->alpha, g, Yq[t], nullptr, J.o1, J.accumulate);
+      push(Xq[t], J.c0, J.o0, J.accumulate, g);
+      push(Yq[t], nullptr, J.o1, J.accumulate, g);
     }
+    flush();
     R.ws.reset(mark);
   }
 }
