@@ -270,9 +270,11 @@ int ckks_lt_batch_workspace_size(const ckks_params* params, int count, const ckk
  * sets of every item that uses a key, so each key is read once per launch,
  * whatever the items' levels).  Other algorithms run the items one after the
  * other.  Results are bit-identical to evaluating each item alone.  Items
- * whose arguments are invalid get an error status and are skipped; outputs
- * must not overlap inputs or each other.  Returns the first error, or
- * CKKS_OK.  Same stream and ownership rules as ckks_lt_eval.
+ * whose arguments are invalid, or whose key set lacks a rotation their split,
+ * stride or centre needs, get that error as their status and are skipped;
+ * the other items still run.  Outputs that overlap inputs or each other fail
+ * every item with CKKS_E_INVALID_ARG before anything runs.  Returns the
+ * first error, or CKKS_OK.  Same stream and ownership rules as ckks_lt_eval.
  */
 int ckks_lt_eval_batch(const ckks_params* params, int count, ckks_lt_item* items, int algo, void* ws,
                        size_t ws_bytes, void* stream);

@@ -98,6 +98,16 @@ hipError_t launch_ns(const ckks_params* P, const BConvArgs& a, int items, hipStr
 // All items of one launch have the same number of source limbs `ns`.
 hipError_t launch_bconv(const ckks_params* P, const BConvArgs& a, int items, int ns, hipStream_t s) {
   if (items <= 0) return hipSuccess;
+  // Launch geometry, checked on the host before anything runs: every item's
+  // plan converts from exactly ns limbs into at most max_nd <= kMaxDst limbs
+  // (so each workgroup's chunk [m0, m1) lies inside the plan and the grid
+  // covers every destination), its buffers are set and the position grid
+  // covers N exactly.
+  if (items > kMaxConv || a.max_nd < 1 || a.max_nd > kMaxDst || P->n % kThreads) return hipErrorInvalidValue;
+  for (int i = 0; i < items; ++i) {
+    const std::pair<int, int> d = P->plan_dims(a.plan[i]);
+    if (d.first != ns || d.second < 1 || d.second > a.max_nd || !a.src[i] || !a.dst[i]) return hipErrorInvalidValue;
+  }
   ProfScope prof(CKKS_KERNEL_BCONV, s, (double)a.limbs_moved * P->n * 8);
   switch (ns) {
     case 1: return launch_ns<1>(P, a, items, s);

@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/ckks_lt.h"
@@ -114,7 +115,7 @@ struct BConvArgs {
   uint64_t* dst[kMaxConv];        // destination limb m at dst + (plan.dst[m] - dst_shift) N
   int dst_shift[kMaxConv];
   int limbs_moved;                // sum over items of ns + nd (timing only)
-  int max_nd;                     // largest nd over the items
+  int max_nd;                     // largest nd over the items (sets the grid's destination chunks)
 };
 
 // Key-switch inner products of ndig digit sets with nkeys keys: output
@@ -243,6 +244,7 @@ struct ckks_params {
   int* d_enc_perm = nullptr;
   double* d_enc_tw = nullptr;
   double* d_enc_zinv = nullptr;
+  std::vector<std::pair<int, int>> plan_shape;  // host copy of each plan's (ns, nd)
   std::vector<int> plan_decomp;        // level * beta_max + b -> plan index
   std::vector<int> plan_moddown, plan_mdrescale, plan_rescale;  // per level
   int beta_max = 0;
@@ -250,4 +252,9 @@ struct ckks_params {
   int beta(int level) const { return (level + alpha) / alpha; }
   int Kmax() const { return alpha + L + 1; }
   const ckks::BConvPlan* plan(int idx) const { return d_plans + idx; }
+  // (ns, nd) of a device plan pointer returned by plan(), read on the host
+  std::pair<int, int> plan_dims(const ckks::BConvPlan* p) const {
+    const ptrdiff_t i = p - d_plans;
+    return (i >= 0 && (size_t)i < plan_shape.size()) ? plan_shape[(size_t)i] : std::pair<int, int>(-1, -1);
+  }
 };

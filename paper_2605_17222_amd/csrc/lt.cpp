@@ -1160,6 +1160,18 @@ static int batch_common(const ckks_params* P, int count, ckks_lt_item* items, in
       if (first_err == CKKS_OK) first_err = e;
       continue;
     }
+    if (!plan_only) {
+      // The item planned alone (no launches) finds what only its own keys
+      // can tell, e.g. a rotation its split, stride or centre needs and its
+      // key set lacks: that item fails, the others still run.
+      Run D = make_run(P, stream, true, nullptr);
+      run_items(D, algo, {&items[t].in}, {&items[t].diags}, {k}, {&items[t].out});
+      if (D.err != CKKS_OK) {
+        items[t].status = D.err;
+        if (first_err == CKKS_OK) first_err = D.err;
+        continue;
+      }
+    }
     ks.push_back(k);
     in.push_back(&items[t].in);
     dg.push_back(&items[t].diags);
@@ -1174,9 +1186,11 @@ static int batch_common(const ckks_params* P, int count, ckks_lt_item* items, in
       for (size_t b = 0; b < in.size(); ++b) {
         const size_t ib = (size_t)(in[b]->level + 1) * N * 8, obb = (size_t)in[b]->level * N * 8;
         for (const void* o : {(const void*)out[a]->c0, (const void*)out[a]->c1}) {
-          if (overlap(o, ob, in[b]->c0, ib) || overlap(o, ob, in[b]->c1, ib)) return CKKS_E_INVALID_ARG;
-          if (a != b && (overlap(o, ob, out[b]->c0, obb) || overlap(o, ob, out[b]->c1, obb)))
+          if (overlap(o, ob, in[b]->c0, ib) || overlap(o, ob, in[b]->c1, ib) ||
+              (a != b && (overlap(o, ob, out[b]->c0, obb) || overlap(o, ob, out[b]->c1, obb)))) {
+            for (int i : idx) items[i].status = CKKS_E_INVALID_ARG;  // nothing runs
             return CKKS_E_INVALID_ARG;
+          }
         }
       }
     }

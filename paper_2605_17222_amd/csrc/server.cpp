@@ -48,6 +48,7 @@ struct Request {
 
 struct Batch {
   std::vector<Request*> reqs;
+  const ckks_params* params = nullptr;  // the ring's, captured under the mutex
   size_t off = 0, bytes = 0;  // arena range
   int slot = 0;               // stream slot
   hipEvent_t done = nullptr;
@@ -145,12 +146,18 @@ bool ckks_server::launch(Batch* b) {
     return true;
   }
   std::vector<ckks_lt_item> items;
-  for (Request* r : b->reqs) items.push_back(r->item);
-  const int e = ckks_lt_eval_batch(rings[b->reqs[0]->ring].params, (int)items.size(), items.data(),
-                                   CKKS_LT_TH_BSGS, arena_base + b->off, b->bytes, streams[b->slot]);
+  for (Request* r : b->reqs) {
+    items.push_back(r->item);
+    items.back().status = CKKS_PENDING;  // not yet written by the call
+  }
+  const int e = ckks_lt_eval_batch(b->params, (int)items.size(), items.data(), CKKS_LT_TH_BSGS,
+                                   arena_base + b->off, b->bytes, streams[b->slot]);
   for (size_t t = 0; t < items.size(); ++t) {
-    // an item without an error of its own takes the call's code
-    b->reqs[t]->item.status = (items[t].status == CKKS_OK && e != CKKS_OK) ? e : items[t].status;
+    // Each item carries its own result (an item whose arguments or keys fail
+    // does not fail the others); an item the call never reached takes the
+    // call's code.
+    const int st = items[t].status;
+    b->reqs[t]->item.status = st == CKKS_PENDING ? (e != CKKS_OK ? e : CKKS_E_DEVICE) : st;
     b->reqs[t]->item.out = items[t].out;  // level and scale set by the call
   }
   if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
@@ -197,6 +204,7 @@ Batch* ckks_server::form_batch() {
   Batch* b = new Batch;
   b->slot = slot;
   b->reqs = take;
+  b->params = rings[ring].params;
   b->bytes = Arena::round(need);
   arena.alloc(b->bytes, &b->off);
   slot_busy[slot] = true;
@@ -256,6 +264,9 @@ void ckks_server::run() {
       const bool ok = launch(b);
       lk.lock();
       if (!ok) {
+        // kernels of the batch may already be on the stream: its arena range
+        // is released only once they have finished
+        if (!simulated()) (void)hipStreamSynchronize(streams[b->slot]);
         retire(b, CKKS_E_DEVICE);
         inflight.erase(std::find(inflight.begin(), inflight.end(), b));
         delete b;

@@ -107,3 +107,30 @@ def test_batch_n16_autotuned_splits():
         assert np.array_equal(g, ref), it["split"]
         z = o.decrypt_slots(g, sc)
         assert np.abs(z - W.matvec(it["diags"], it["v"])).max() <= 1e-4
+
+
+def test_batch_item_missing_key_fails_alone():
+    # One item's key set lacks a rotation its split needs: that item alone
+    # gets CKKS_E_UNSUPPORTED, the other item of the batch is still exact.
+    import torch
+    prm = W.params_toy()
+    o, keys, items, delta = _batch_case(prm, [(2, 16, (2, 2, 4)), (2, 16, (2, 2, 4))], 11)
+    P = gpu_params(prm)
+    dkeys = {r: limbs_tensor(k) for r, k in keys.items()}
+    short = {r: k for r, k in dkeys.items() if r != 2}  # the middle rotation n1 = 2 is gone
+    assert len(short) == len(dkeys) - 1
+    batch, keep = [], []
+    for it, ks in zip(items, (dkeys, short)):
+        c0, c1 = limbs_tensor(it["ct"][0]), limbs_tensor(it["ct"][1])
+        pts = [limbs_tensor(f) for f in it["pts"]]
+        keep += [c0, c1, pts]
+        batch.append(H.BatchItem(2, delta, c0, c1, (2, 2, 4), pts, delta, ks, H.empty((2, prm.n)),
+                                 H.empty((2, prm.n))))
+    wsb = H.ckks_lt_batch_workspace_size(P, batch, H.CKKS_LT_TH_BSGS)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    code = H.ckks_lt_eval_batch(P, batch, H.CKKS_LT_TH_BSGS, ws, wsb)
+    torch.cuda.synchronize()
+    assert code == H.CKKS_E_UNSUPPORTED
+    assert batch[0].status == H.CKKS_OK and batch[1].status == H.CKKS_E_UNSUPPORTED
+    ref = o.lt_th(2, items[0]["ct"], (2, 2, 4), items[0]["pts"], keys)
+    assert np.array_equal(np.stack([H.to_host(batch[0].out0), H.to_host(batch[0].out1)]), ref)

@@ -114,3 +114,32 @@ def test_server_serving_split_n14():
     mix, st = _serve([r14], order, 8 << 30, max_batch=4, max_inflight=2)
     assert st["completed"] == 3
     _check([r14], mix, 1e-4)
+
+
+def test_server_request_missing_key_fails_alone():
+    # The ring lacks rotation 8, which only the (2, 2, 4) request needs.  The
+    # requests behind the first queue while it runs, so the bad one is
+    # batched with good ones: it alone fails, the others are bit-exact.
+    import torch
+    prm = W.params_toy()
+    specs = [(2, 8, (1, 4, 2)), (2, 16, (2, 2, 4)), (2, 8, (1, 4, 2)), (2, 6, (1, 4, 2))]
+    R = Ring(prm, specs, 51)
+    short = {r: k for r, k in R.dkeys.items() if r != 8}
+    assert len(short) == len(R.dkeys) - 1
+    torch.cuda.synchronize()
+    outs, ids = [], []
+    with H.Server(64 * MiB, max_batch=4, max_inflight=1) as S:
+        ring = H.ckks_server_add_ring(S, R.P, short)
+        for t, it in enumerate(R.items):
+            c0, c1, pts = R.dev[t]
+            o0, o1 = H.empty((2, prm.n)), H.empty((2, prm.n))
+            outs.append((o0, o1))
+            ids.append(H.ckks_server_submit(S, ring, 2, R.delta, c0, c1, it["split"], pts, R.delta, o0, o1))
+        H.ckks_server_wait_all(S)
+        sts = [H.ckks_server_poll(S, i)[0] for i in ids]
+    assert sts[1] == H.CKKS_E_UNSUPPORTED
+    for t in (0, 2, 3):
+        assert sts[t] == H.CKKS_OK, t
+        it = R.items[t]
+        ref = R.o.lt_th(2, it["ct"], it["split"], it["pts"], R.keys)
+        assert np.array_equal(np.stack([H.to_host(outs[t][0]), H.to_host(outs[t][1])]), ref), t
