@@ -209,6 +209,27 @@ int ckks_lt_workspace_size(const ckks_params* params, int level, const ckks_lt_d
 int ckks_lt_eval(const ckks_params* params, const ckks_ct* in, const ckks_lt_diags* diags,
                  const ckks_rotkeys* keys, int algo, ckks_ct* out, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * LT as ckks_lt_eval, with its workspace taken from a scratch array of
+ * CKKS_LT_NOALLOC_MAX_WS bytes that the library holds on each device it runs
+ * on (made when the library's code is loaded there, kept until the process
+ * ends).  The call allocates no device memory and frees none; the caller
+ * still passes the inputs, keys, plaintexts and outputs.  An LT whose
+ * workspace (ckks_lt_workspace_size) exceeds CKKS_LT_NOALLOC_MAX_WS is
+ * refused with CKKS_E_WORKSPACE before anything is enqueued.  Every call on
+ * one device uses that device's one scratch array, which keeps the previous
+ * call's contents (the LT reads no workspace word it has not written):
+ * calls whose work overlaps on one device race, so the caller orders them
+ * (one stream, or events between streams).  Other arguments, results and
+ * errors as ckks_lt_eval.
+ */
+#define CKKS_LT_NOALLOC_MAX_WS ((size_t)64 << 20)
+
+int ckks_lt_eval_noalloc(const ckks_params* params, const ckks_ct* in, const ckks_lt_diags* diags,
+                         const ckks_rotkeys* keys, int algo, ckks_ct* out, void* stream);
+
 /* ---- plaintext encoding on the device ------------------------------------- */
 /*
  * Encoding (Section II-A): the plaintext of a vector z of N/2 complex slots

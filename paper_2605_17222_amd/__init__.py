@@ -44,7 +44,11 @@ EXPORTED = [
     "ckks_lt_predict", "ckks_server_create", "ckks_server_add_ring", "ckks_server_submit", "ckks_server_poll",
     "ckks_server_result", "ckks_server_cancel", "ckks_server_wait_all", "ckks_server_stats", "ckks_server_destroy",
     "ckks_encode_workspace_size", "ckks_encode", "ckks_th_traffic_model", "ckks_packed_poly_bytes", "ckks_pack",
+    "ckks_lt_eval_noalloc",
 ]
+
+# Largest workspace ckks_lt_eval_noalloc serves (its per-device scratch array).
+CKKS_LT_NOALLOC_MAX_WS = 64 << 20
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
            "automorph", "keyswitch_gather", "encode_fft"]
@@ -160,6 +164,9 @@ def lib() -> ctypes.CDLL:
         L.ckks_lt_eval.argtypes = [ctypes.c_void_p, ctypes.POINTER(Ct), ctypes.POINTER(Diags),
                                    ctypes.POINTER(RotKeys), ctypes.c_int, ctypes.POINTER(Ct), ctypes.c_void_p,
                                    ctypes.c_size_t, ctypes.c_void_p]
+        L.ckks_lt_eval_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(Ct), ctypes.POINTER(Diags),
+                                           ctypes.POINTER(RotKeys), ctypes.c_int, ctypes.POINTER(Ct),
+                                           ctypes.c_void_p]
         L.ckks_op_ntt.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]
         L.ckks_op_decompose.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -328,6 +335,21 @@ def ckks_lt_workspace_size(params: Params, level: int, split: Sequence[int], pts
     _check(lib().ckks_lt_workspace_size(params, level, ctypes.byref(d), algo, ctypes.byref(out)),
            "ckks_lt_workspace_size")
     return out.value
+
+
+def ckks_lt_eval_noalloc(params: Params, level: int, scale: float, c0, c1, split: Sequence[int], pts: Sequence,
+                         pt_scale: float, keys: Optional[Dict[int, object]], algo: int, out0, out1, stream=None,
+                         stride: int = 1, centre: int = 0, onfly: bool = False) -> Tuple[int, float]:
+    """ckks_lt_eval with the library's per-device scratch as its workspace
+    (no device allocation; workspaces above CKKS_LT_NOALLOC_MAX_WS raise
+    CKKS_E_WORKSPACE).  Returns (out level, out scale)."""
+    cin = Ct(level, scale, _ptr(c0), _ptr(c1))
+    cout = Ct(level - 1, 0.0, _ptr(out0), _ptr(out1))
+    d, keep1 = _diags(split, pts, pt_scale, stride, centre, onfly)
+    k, keep2 = _keys(keys)
+    _check(lib().ckks_lt_eval_noalloc(params, ctypes.byref(cin), ctypes.byref(d), ctypes.byref(k), algo,
+                                      ctypes.byref(cout), _stream(stream)), "ckks_lt_eval_noalloc")
+    return cout.level, cout.scale
 
 
 def ckks_lt_eval(params: Params, level: int, scale: float, c0, c1, split: Sequence[int], pts: Sequence,

@@ -214,6 +214,10 @@ struct EncArgs {
   int64_t* coef[kMaxEnc];
 };
 
+// Device address of the no-allocation entry point's scratch array on
+// `device` (which must be current), looked up on first use and kept.
+int scratch_address(int device, void** out);
+
 // Kernel launchers.
 hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
                       hipStream_t s);

@@ -1082,6 +1082,20 @@ int ckks_lt_eval(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* d
   }
 }
 
+int ckks_lt_eval_noalloc(const ckks_params* P, const ckks_ct* in, const ckks_lt_diags* diags,
+                         const ckks_rotkeys* keys, int algo, ckks_ct* out, void* stream) {
+  if (!P) return CKKS_E_INVALID_ARG;
+  void* ws = nullptr;
+  {
+    DeviceGuard dg(P->device);
+    const int e = scratch_address(P->device, &ws);
+    if (e != CKKS_OK) return e;
+  }
+  // ckks_lt_eval plans first and refuses a workspace beyond the scratch
+  // before it enqueues anything.
+  return ckks_lt_eval(P, in, diags, keys, algo, out, ws, CKKS_LT_NOALLOC_MAX_WS, stream);
+}
+
 static int encode_common(const ckks_params* P, int count, const ckks_encode_item* items, double scale,
                          int first_prime, int n_limbs, void* ws, size_t ws_bytes, void* stream, bool plan_only,
                          size_t* need) {
