@@ -37,11 +37,6 @@ struct PrimeDev {
   uint64_t pk_off;         // byte offset of this limb in a packed PQ polynomial
   int narrow;              // q < 2^40: packed as a 32-bit and an 8-bit plane
   int pk_pad;
-  // Twiddles of the column stages (the first kColLog stages of the forward
-  // transform, the last of the inverse) as integers with Shoup companions,
-  // for every prime: ctw[dir][0][i] = rho^br(i), ctw[dir][1][i] its Shoup
-  // word, i = 1 .. 15, rho = psi (dir 0) or psi^-1 (dir 1).
-  uint64_t ctw[2][2][16];
 };
 
 // Packed storage of resident operands (keys, plaintexts): a limb of a prime
@@ -53,11 +48,9 @@ constexpr uint64_t kNarrowLimit = 1ull << 40;
 
 constexpr uint64_t kFpPrimeLimit = 1ull << 46;
 
-// The two NTT passes split N = 16 (N / 16): the column pass does the first
-// kColLog = 4 stages on the N/16 columns of 16 words (stride N/16), the row
-// pass the last log2 N - 4 stages on the 16 contiguous rows of N/16 words.
-constexpr int kColLog = 4;
-__host__ __device__ inline int ntt_row_log(int log_n) { return log_n - kColLog; }
+// The two NTT passes split log2 N = (log2 N - B) + B: the column pass does the
+// first log2 N - B stages, the row pass the last B.
+__host__ __device__ inline int ntt_row_log(int log_n) { return log_n / 2; }
 
 // Row-pass twiddles factor (fp primes): stage s (0 <= s < B) of row `row` uses
 // rho^br(2^(log N - B + s) + row 2^s + y), y < 2^s, with rho = psi or psi^-1
@@ -82,8 +75,6 @@ struct BConvPlan {
   uint64_t hmod[kMaxDst][kMaxSrc];  // [S/s_j]_{d_m} * 2^64 mod d_m
   uint64_t sinv[kMaxDst];           // S^-1 mod d_m
   uint64_t sinv_sh[kMaxDst];
-  uint64_t hinvn[kMaxSrc];          // hinv * N^-1 mod s_j: the inverse NTT's last factor
-  uint64_t hinvn_sh[kMaxSrc];       // folded into the conversion's first (Shoup companion)
   int split30;                      // every source and destination prime < 2^60: the
                                     // inner product may use 30-bit column sums
   uint32_t hk[kMaxDst][kMaxSrc][2];  // hmod split into its 30-bit halves (split30)
@@ -117,20 +108,14 @@ struct NttArgs {
 // out = (aux - v) * S^-1 mod q.
 enum EpiMode { EPI_NONE = 0, EPI_SUBMUL = 1 };
 
-// Basis conversions fused with the column stages around them (Decompose's
-// ModUp, the division of ModDown / rescale): for each item, the source limbs
-// arrive as the inverse NTT's row-pass output, their column stages finish the
-// inverse transform, eq. (3) converts, and the forward transform's column
-// stages of every destination limb run before it is stored (for its row pass).
 constexpr int kMaxConv = 8;
 struct BConvArgs {
   const BConvPlan* plan[kMaxConv];
-  const uint64_t* src[kMaxConv];  // source limb j at src + j N (inverse row-pass output)
+  const uint64_t* src[kMaxConv];  // source limb j at src + j N
   uint64_t* dst[kMaxConv];        // destination limb m at dst + (plan.dst[m] - dst_shift) N
   int dst_shift[kMaxConv];
   int limbs_moved;                // sum over items of ns + nd (timing only)
-  int max_nd;                     // largest nd over the items
-  int chunk;                      // destination limbs per workgroup (grid.z = ceil(max_nd / chunk))
+  int max_nd;                     // largest nd over the items (sets the grid's destination chunks)
 };
 
 // Key-switch inner products of ndig digit sets with nkeys keys: output
@@ -236,12 +221,7 @@ int scratch_address(int device, void** out);
 // Kernel launchers.
 hipError_t launch_ntt(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
                       hipStream_t s);
-// One pass: the row pass (the inverse transform's first, the forward's last,
-// with the epilogue) or the column pass.
-hipError_t launch_ntt_row(const struct ::ckks_params* P, bool forward, const NttArgs& a, int total_limbs, int epi,
-                          hipStream_t s);
 hipError_t launch_bconv(const struct ::ckks_params* P, const BConvArgs& a, int items, int ns, hipStream_t s);
-int bconv_chunk_max();  // largest BConvArgs::chunk
 hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipStream_t s);
 hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGatherArgs& a, hipStream_t s);
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);

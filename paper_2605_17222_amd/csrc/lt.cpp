@@ -59,17 +59,14 @@ LimbRange range(const uint64_t* in, uint64_t* out, int prime0, int count, const 
   return r;
 }
 
-// Collects limb ranges into NTT launches (flushing when the table is full):
-// whole transforms, or only the row pass (row_only) when a basis conversion
-// does the column stages.
+// Collects limb ranges into NTT launches (flushing when the table is full).
 struct NttBatch {
   Run& R;
   bool fwd;
   int epi;
-  bool row_only;
   NttArgs a;
   int total = 0;
-  NttBatch(Run& r, bool f, int e = EPI_NONE, bool ro = false) : R(r), fwd(f), epi(e), row_only(ro) { a.nr = 0; }
+  NttBatch(Run& r, bool f, int e = EPI_NONE) : R(r), fwd(f), epi(e) { a.nr = 0; }
   void add(const LimbRange& r) {
     if (r.count <= 0) return;
     if (a.nr == kMaxRanges) flush();
@@ -77,26 +74,12 @@ struct NttBatch {
     total += r.count;
   }
   void flush() {
-    if (a.nr && R.live())
-      R.check(row_only ? launch_ntt_row(R.P, fwd, a, total, epi, R.s) : launch_ntt(R.P, fwd, a, total, epi, R.s));
+    if (a.nr && R.live()) R.check(launch_ntt(R.P, fwd, a, total, epi, R.s));
     a.nr = 0;
     total = 0;
   }
   ~NttBatch() { flush(); }
 };
-
-// Destination limbs per workgroup of a basis-conversion launch (the tile
-// shape of bconv.hip along the destinations): whole conversions when the
-// launch has enough workgroups to fill the device, else chunks, down to 8
-// limbs, until it has about kConvTargetWg (each chunk repeats the sources'
-// column stages, so smaller chunks cost more work).
-constexpr int kConvTargetWg = 512;
-int conv_chunk(const ckks_params* P, int items, int max_nd) {
-  const int tiles = std::max(1, (P->n >> kColLog) / 64);
-  int z = (max_nd + bconv_chunk_max() - 1) / bconv_chunk_max();
-  while ((long)tiles * items * z < kConvTargetWg && (max_nd + z) / (z + 1) >= 8) ++z;
-  return (max_nd + z - 1) / z;
-}
 
 // Collects basis conversions with the same number of source limbs.
 struct BConvBatch {
@@ -120,10 +103,7 @@ struct BConvBatch {
     ++items;
   }
   void flush() {
-    if (items && R.live()) {
-      a.chunk = conv_chunk(R.P, items, a.max_nd);
-      R.check(launch_bconv(R.P, a, items, ns, R.s));
-    }
+    if (items && R.live()) R.check(launch_bconv(R.P, a, items, ns, R.s));
     reset();
   }
   ~BConvBatch() { flush(); }
@@ -140,10 +120,8 @@ typedef std::vector<Job> Jobs;
 // ---- Decompose, ModDown, rescale -----------------------------------------------
 
 // Decompose (Fig. 1) of level-l Q-basis polynomials (NTT form) into digits
-// [beta_l][alpha+l+1][N]: the inverse NTT's row pass (which also stores each
-// group's own limbs, unchanged, into its digit: ModUp keeps them, R15), the
-// basis conversion with the column stages of both transforms, and the
-// forward NTT's row pass of the converted limbs.
+// [beta_l][alpha+l+1][N].  The inverse NTT's first pass also stores each
+// group's own limbs, unchanged, into its digit (ModUp keeps them, R15).
 void decompose(Run& R, const Jobs& xs) {
   const ckks_params* P = R.P;
   const int a = P->alpha;
@@ -152,7 +130,7 @@ void decompose(Run& R, const Jobs& xs) {
   for (size_t t = 0; t < xs.size(); ++t) coef[t] = R.limbs(xs[t].level + 1);
   if (R.live()) {
     {
-      NttBatch inv(R, false, EPI_NONE, true);
+      NttBatch inv(R, false);
       for (size_t t = 0; t < xs.size(); ++t) {
         const int level = xs[t].level, K = P->K(level);
         for (int b = 0; b < P->beta(level); ++b) {
@@ -175,7 +153,7 @@ void decompose(Run& R, const Jobs& xs) {
       }
       for (auto& kv : by_ns) delete kv.second;  // flushes
     }
-    NttBatch fwd(R, true, EPI_NONE, true);
+    NttBatch fwd(R, true);
     for (size_t t = 0; t < xs.size(); ++t) {
       const int level = xs[t].level, K = P->K(level);
       for (int b = 0; b < P->beta(level); ++b) {
@@ -195,9 +173,8 @@ enum DivKind { DIV_MODDOWN, DIV_MODDOWN_RESCALE, DIV_RESCALE };
 //  DIV_MODDOWN:         x [alpha+l+1] -> out [l+1], divide by P
 //  DIV_MODDOWN_RESCALE: x [alpha+l+1] -> out [l],   divide by P q_l
 //  DIV_RESCALE:         x [l+1]       -> out [l],   divide by q_l
-// Inverse row pass of the dividing limbs -> basis conversion onto the kept
-// limbs (with both transforms' column stages) -> forward row pass, which
-// applies out = (kept - conv) * divisor^-1.
+// INTT of the dividing limbs -> BConv onto the kept limbs -> NTT whose last
+// pass applies out = (kept - conv) * divisor^-1.
 void divide(Run& R, DivKind kind, const Jobs& xs) {
   const ckks_params* P = R.P;
   const int a = P->alpha;
@@ -214,7 +191,7 @@ void divide(Run& R, DivKind kind, const Jobs& xs) {
     };
     auto nout_of = [&](int level) { return kind == DIV_MODDOWN ? level + 1 : level; };
     {
-      NttBatch inv(R, false, EPI_NONE, true);
+      NttBatch inv(R, false);
       for (size_t t = 0; t < xs.size(); ++t) {
         const uint64_t* x = xs[t].in;
         const int level = xs[t].level;
@@ -232,7 +209,7 @@ void divide(Run& R, DivKind kind, const Jobs& xs) {
       for (size_t t = 0; t < xs.size(); ++t)
         bc.add(plan_of(xs[t].level), nout_of(xs[t].level), coef[t], xs[t].out, a);
     }
-    NttBatch fwd(R, true, EPI_SUBMUL, true);
+    NttBatch fwd(R, true, EPI_SUBMUL);
     for (size_t t = 0; t < xs.size(); ++t) {
       const int level = xs[t].level;
       const BConvPlan* plan = plan_of(level);

@@ -68,7 +68,7 @@ uint64_t neg_inv64(uint64_t q) {
 
 // Fill a plan for the conversion src -> dst (PQ indices).  sinv: product of
 // the source primes inverted modulo each destination prime.
-int make_plan(const std::vector<uint64_t>& pr, uint64_t n, const std::vector<int>& src, const std::vector<int>& dst,
+int make_plan(const std::vector<uint64_t>& pr, const std::vector<int>& src, const std::vector<int>& dst,
               BConvPlan* pl) {
   if ((int)src.size() > kMaxSrc || (int)dst.size() > kMaxDst || src.empty()) return CKKS_E_UNSUPPORTED;
   memset(pl, 0, sizeof(*pl));
@@ -93,8 +93,6 @@ int make_plan(const std::vector<uint64_t>& pr, uint64_t n, const std::vector<int
       if (i != j) h = mm(h, pr[src[i]] % sj, sj);
     pl->hinv[j] = inv(h, sj);
     pl->hinv_sh[j] = shoup_of(pl->hinv[j], sj);
-    pl->hinvn[j] = mm(pl->hinv[j], inv(n % sj, sj), sj);
-    pl->hinvn_sh[j] = shoup_of(pl->hinvn[j], sj);
   }
   for (int m = 0; m < pl->nd; ++m) {
     const uint64_t d = pr[dst[m]];
@@ -234,13 +232,6 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
       }
     }
     PrimeDev& c = pd[i];
-    for (int k = 0; k < 16; ++k) {
-      const uint32_t r = brev(k, P->log_n);
-      c.ctw[0][0][k] = pf[r];
-      c.ctw[0][1][k] = shoup_of(pf[r], q);
-      c.ctw[1][0][k] = pi[r];
-      c.ctw[1][1][k] = shoup_of(pi[r], q);
-    }
     c.fp = fp ? 1 : 0;
     c.qd = (double)q;
     c.qinv_d = 1.0 / (double)q;
@@ -267,7 +258,7 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
   std::vector<BConvPlan> plans;
   auto add_plan = [&](const std::vector<int>& src, const std::vector<int>& dst) -> int {
     plans.emplace_back();
-    int e = make_plan(P->primes, (uint64_t)P->n, src, dst, &plans.back());
+    int e = make_plan(P->primes, src, dst, &plans.back());
     if (e != CKKS_OK) return e;
     return (int)plans.size() - 1;
   };
