@@ -30,14 +30,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CKKS LT evals/s and HBM GB/s at N=2^16, 64 diags; batched vs plain BSGS"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of a kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# (KiB per dispatch) scaled by what the counters read for a plain 256 MiB copy
-# kernel (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see profiles/.  None once the
-# kernel has changed since the counters were taken.
-TRAFFIC = {
-    # mac_kernel<4, false> at N=2^16, level 24, TH-BSGS (4,4,4): (2 x 831079.8 + 139265.5) KiB
-    "ptmac": (2 * 831079.8 + 139265.5) * 1024,
-}
+# rocprofv3 summaries of `bench.py --profile-only` (TH-BSGS (4,4,4) and plain
+# BSGS (8,8) at N=2^16, level 24, 64 diagonals), written by
+# paper_2605_17222_amd.profiling; their figures are used only while the
+# library's sources are the ones that were profiled.
+PROFILES = os.path.join(ROOT, "profiles")
+PROFILE_TRACE = os.path.join(PROFILES, "kernel_trace_th444_bsgs88_n16_l24_d64.md")
+PROFILE_HBM = os.path.join(PROFILES, "hbm_counters_th444_bsgs88_n16_l24_d64.md")
+PROFILE_VALU = os.path.join(PROFILES, "valu_counters_th444_bsgs88_n16_l24_d64.md")
+# The kernel (and template instance) behind each timed kernel id in one
+# TH-BSGS (4,4,4) step at level 24, as rocprofv3 names it.
+TH444_KERNEL = {"ptmac": "mac_kernel<4, false>", "keyswitch_gather": "ks_gather_kernel<false, 3>"}
 
 
 def parse():
@@ -48,6 +51,7 @@ def parse():
                     help="untimed steps before each timed single-LT leg (the device's clocks ramp up over the "
                          "first 10-20 steps after an idle gap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-case", default=None, help=argparse.SUPPRESS)  # one oracle timing, JSON (child process)
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baseline (for rocprofv3)")
     ap.add_argument("--packed", action="store_true",
                     help="with --profile-only: keys and TH-BSGS plaintexts in the packed layout")
@@ -153,12 +157,6 @@ def step_percentiles(P, prm, level, split, reps, torch, H, warmup=50):
     pick = lambda f: round(ms[min(reps - 1, int(f * reps))], 4)
     del ws, keys, pts
     return {"steps": reps, "p10_ms": pick(0.1), "p50_ms": pick(0.5), "p90_ms": pick(0.9)}
-
-
-# Measured on MI355X with a multiply-add probe: a Shoup modular multiplication
-# (64-bit) issues at about 1.2 T/s over the whole device (v_mad_u64_u32 and
-# FP64 FMA both run at about 30 T/s).
-SHOUP_PEAK_T_PER_S = 1.2
 
 
 def onfly_leg(P, prm, level, split, n_diag, steps, warmup, torch, H, seed=99, algo="th"):
@@ -295,29 +293,148 @@ def compulsory_bytes(prm, level, split, algo):
     return words * 8
 
 
-def cpu_baseline(prm, level, split):
-    """The oracle's TH-BSGS LT on this host (keys and encoding excluded from timing)."""
+def host_cpu():
+    """Model name, logical CPUs and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "usable_cpus": usable}
+
+
+def cpu_case(name):
+    """One oracle case, timed in this process (the thread count is the
+    OpenMP default of the environment): LT evaluation only, keygen,
+    encryption and encoding excluded.  Returns a dict (printed as JSON by
+    --cpu-case)."""
     import numpy as np
     import oracle as O
     import workload as W
-    w = W.workload_n16(level=level, th_split=split)
-    o = O.Oracle(w.params)
-    o.keygen(11)
-    delta = 2.0 ** w.params.log_delta
-    ct = o.encrypt(w.level, w.vector, delta, seed=5)
-    keys = o.rotkeys(W.th_rotations(*split))
-    pts = o.th_plaintexts(w.diags, *split, delta)
+    budget = float(os.environ.get("CKKS_CPU_CASE_SECONDS", "10"))
+    if name in ("th444", "bsgs88"):
+        w = W.workload_n16(level=24)
+    elif name in ("toy_th", "toy_bsgs"):
+        w = W.workload_toy()
+    elif name == "chain":
+        w = None
+    else:
+        raise ValueError(name)
+    if name == "chain":
+        prm = W.params_n16()
+        o = O.Oracle(prm)
+        o.keygen(11)
+        delta = 2.0 ** prm.log_delta
+        stages = W.dft_chain(3, prm)
+        rots = set()
+        for st in stages:
+            rots |= set(W.th_rotations(*st.split, stride=st.stride, centre=st.centre, slots=prm.slots))
+        keys = o.rotkeys(sorted(rots))
+        pts = [o.th_plaintexts(st.diags, *st.split, delta, stride=st.stride, centre=st.centre) for st in stages]
+        v = W.input_vector(3, prm.slots)
+        ct = o.encrypt(24, v, delta, seed=5)
+
+        def run():
+            x, lv = ct, 24
+            for st, pt in zip(stages, pts):
+                x = o.lt_th(lv, x, st.split, pt, keys, stride=st.stride, centre=st.centre)
+                lv -= 1
+            return x
+        what = "4-stage DFT-like chain at N=2^16, level 24 -> 20 (18 keys)"
+    else:
+        prm = w.params
+        o = O.Oracle(prm)
+        o.keygen(11)
+        delta = 2.0 ** prm.log_delta
+        ct = o.encrypt(w.level, w.vector, delta, seed=5)
+        if name.endswith("th") or name == "th444":
+            keys = o.rotkeys(W.th_rotations(*w.th_split))
+            pts = o.th_plaintexts(w.diags, *w.th_split, delta)
+            run = lambda: o.lt_th(w.level, ct, w.th_split, pts, keys)  # noqa: E731
+            what = "TH-BSGS %s LT, N=2^%d, level %d, %d diagonals" % (w.th_split, prm.log_n, w.level, len(w.diags))
+        else:
+            keys = o.rotkeys(W.bsgs_rotations(*w.bsgs_split))
+            pts = o.bsgs_plaintexts(w.diags, *w.bsgs_split, delta)
+            run = lambda: o.lt_bsgs(w.level, ct, w.bsgs_split, pts, keys)  # noqa: E731
+            what = "plain BSGS %s LT, N=2^%d, level %d, %d diagonals" % (w.bsgs_split, prm.log_n, w.level,
+                                                                         len(w.diags))
     reps, t_total = 0, 0.0
-    while reps < 3 and t_total < 10.0:
+    while reps < 1 or (t_total < budget and reps < 20):
         t0 = time.perf_counter()
-        out = o.lt_th(w.level, ct, split, pts, keys)
+        out = run()
         t_total += time.perf_counter() - t0
         reps += 1
-    err = float(np.abs(o.decrypt_slots(out, delta * delta / w.params.q[level]) - W.matvec(w.diags, w.vector)).max())
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": reps / t_total, "unit": "LT/s", "cores": threads, "kind": "oracle",
-            "sample": "%d full TH-BSGS (4,4,4) LT(s) at N=2^16, level 24, 64 diagonals, real keys; "
-                      "keygen/encoding excluded; decrypted max err %.1e" % (reps, err)}
+    res = {"case": name, "what": what, "reps": reps, "s_per_lt": t_total / reps, "lt_per_s": reps / t_total,
+           "threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or None}
+    if w is not None:
+        lv = w.level
+        sc = delta * delta / prm.q[lv]
+        res["decrypt_max_err"] = float(np.abs(o.decrypt_slots(out, sc) - W.matvec(w.diags, w.vector)).max())
+    return res
+
+
+def _cpu_subprocess(name, threads, seconds):
+    """cpu_case in a child process with OMP_NUM_THREADS = threads (no GPU use)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), CKKS_CPU_CASE_SECONDS=str(seconds))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-case", name], env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        return {"case": name, "threads": threads, "error": (r.stderr or r.stdout)[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    d["threads"] = threads
+    return d
+
+
+def cpu_baseline(prm, level, split, H, specs_batch=None, serving=None):
+    """The oracle (plain C++, u128 arithmetic, OpenMP over limbs) timed on this
+    host: the benchmark's TH-BSGS (4,4,4) LT on all usable cores (`value`) and
+    on one thread, plain BSGS (8,8), the toy configuration and the DFT-like
+    chain; the ragged batch and the serving mix are extrapolated from the
+    measured (4,4,4) time with the operation-count model (labelled as such)."""
+    host = host_cpu()
+    allc = host["usable_cpus"]
+    th_all = _cpu_subprocess("th444", allc, 8)
+    th_one = _cpu_subprocess("th444", 1, 1)
+    cases = {"th444_single_thread": th_one,
+             "bsgs88_all_cores": _cpu_subprocess("bsgs88", allc, 1),
+             "toy_th_all_cores": _cpu_subprocess("toy_th", allc, 2),
+             "toy_th_single_thread": _cpu_subprocess("toy_th", 1, 2),
+             "chain_all_cores": _cpu_subprocess("chain", allc, 1)}
+    res = {"value": th_all.get("lt_per_s"), "unit": "LT/s", "cores": allc, "kind": "oracle",
+           "sample": "%s TH-BSGS (4,4,4) LT(s) at N=2^16, level 24, 64 diagonals on %d threads (real keys and "
+                     "plaintexts; keygen, encryption and encoding excluded; decrypted max err %s)" % (
+                         th_all.get("reps"), allc, "%.1e" % th_all["decrypt_max_err"]
+                         if "decrypt_max_err" in th_all else "n/a"),
+           "host": host, "th444_all_cores": th_all}
+    res.update(cases)
+    # extrapolations: oracle seconds scale with the model's modular multiplications
+    if "s_per_lt" in th_all:
+        base = H.ckks_lt_cost_model(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, split)["modmul"]
+        t_mm = th_all["s_per_lt"] / base
+        if specs_batch:
+            mm = sum(H.ckks_lt_cost_model(prm.log_n, lv, prm.alpha, H.CKKS_LT_TH_BSGS, sp)["modmul"]
+                     for lv, _, sp in specs_batch)
+            res["ragged_batch_extrapolated"] = {"items": len(specs_batch), "s_per_batch": round(mm * t_mm, 2),
+                                                "lt_per_s": round(len(specs_batch) / (mm * t_mm), 4),
+                                                "note": "extrapolated, not measured: the measured (4,4,4) time per "
+                                                        "modular multiplication times each item's model count"}
+        if serving:
+            mm = sum(H.ckks_lt_cost_model(ln, lv, prm.alpha, H.CKKS_LT_TH_BSGS, (4, 16, 4))["modmul"]
+                     for ln, lv in serving) / len(serving)
+            res["serving_extrapolated"] = {"mean_s_per_request": round(mm * t_mm, 3),
+                                           "max_sustained_req_per_s": round(1.0 / (mm * t_mm), 3),
+                                           "note": "extrapolated, not measured: mean model count of the serving "
+                                                   "stream's requests (split (4,16,4)) at the measured rate; at "
+                                                   "200 req/s offered the oracle would fall behind"}
+    return res
 
 
 def ragged_specs(prm, items, H, seed=77):
@@ -571,6 +688,9 @@ def serving_leg(seconds, rate, torch, H, budget_total=200e9, seed=2024, onfly=Fa
 
 def main():
     args = parse()
+    if args.cpu_case:
+        print(json.dumps(cpu_case(args.cpu_case)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
@@ -617,28 +737,67 @@ def main():
     bs_ms = ms_ev_b / bs_steps
 
     n_l, ms_l, bytes_l = prof_dom[dom]
-    achieved = bytes_l / (ms_l * 1e-3) / 1e9
+    avg_s = ms_l / n_l * 1e-3
+    K = prm.alpha + level + 1
+    # Section 8(d)'s algorithmic unit of the dominant kernel: for the
+    # plaintext multiply-accumulate, the plaintexts it streams (17 MiB per
+    # diagonal: K limbs of N words), every present diagonal of the step read
+    # once; for other kernels, each input and output word once (the library's
+    # own count)
+    if dom == "ptmac":
+        unit_bytes = 64 * K * prm.n * 8 / (n_l / args.steps)
+        unit = "plaintext bytes per launch (17 MiB per diagonal: %d limbs x %d words x 8 B; 64 diagonals)" % (K, prm.n)
+    else:
+        unit_bytes = bytes_l / n_l
+        unit = "algorithmic bytes per launch (each input and output word once)"
+    achieved = unit_bytes / avg_s / 1e9
+    hbm = None
+    try:
+        from paper_2605_17222_amd import profiling
+        hbm = profiling.current_block(PROFILE_HBM)
+        trace_blk = profiling.current_block(PROFILE_TRACE)
+        valu_blk = profiling.current_block(PROFILE_VALU)
+    except Exception:  # summaries absent or unreadable: no counter figures
+        trace_blk = valu_blk = None
+    kname = TH444_KERNEL.get(dom)
+    traffic = None
+    if hbm and kname in hbm["kernels"]:
+        traffic = hbm["kernels"][kname]["hbm_bytes"]
+    sched = bytes_l / n_l
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(dom), "traffic_unit": "bytes/launch",
-                "launches_per_step": n_l / args.steps, "avg_launch_us": round(ms_l / n_l * 1e3, 2),
-                "algorithmic_bytes_per_launch": round(bytes_l / n_l), "share_of_step": round(ms_l / ms_ev, 3)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
+                "traffic_source": os.path.relpath(PROFILE_HBM, ROOT) if traffic else None,
+                "traffic_over_unit_bytes": round(traffic / unit_bytes, 3) if traffic else None,
+                "algorithmic_unit": unit, "unit_bytes_per_launch": round(unit_bytes),
+                "launches_per_step": n_l / args.steps, "avg_launch_us": round(avg_s * 1e6, 2),
+                "profiled_avg_launch_us": (trace_blk["kernels"][kname]["avg_us"]
+                                           if trace_blk and kname in trace_blk["kernels"] else None),
+                "schedule_bytes_per_launch": round(sched),
+                "schedule_GB_per_s": round(sched / avg_s / 1e9, 1),
+                "schedule_frac": round(sched / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                "schedule_note": "every operand the launch streams read once: the (a_m, b_m) rotation products, the "
+                                 "plaintexts and the accumulators" if dom == "ptmac" else None,
+                "share_of_step": round(ms_l / ms_ev, 3)}
     breakdown = {k: {"launches_per_step": v[0] / probe_steps, "ms_per_step": round(v[1] / probe_steps, 4),
                      "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}
                  for k, v in prof.items() if v[0]}
     comp = compulsory_bytes(prm, level, th_split, "th")
-    # the VALU side (NTT, BConv): the operation-count model's modular
-    # multiplications against the measured Shoup rate, and the NTT butterflies
-    # against the NTT passes' own time
-    cost = H.ckks_lt_cost_model(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, th_split)
-    ntt_ms = sum(breakdown[k]["ms_per_step"] for k in breakdown if k.startswith("ntt_"))
-    butterflies = cost["ntt_limbs"] * (prm.n // 2) * prm.log_n
-    valu = {"modmul_per_lt": cost["modmul"], "modmul_T_per_s": round(cost["modmul"] / (ms_step * 1e-3) / 1e12, 3),
-            "peak_T_per_s": SHOUP_PEAK_T_PER_S,
-            "frac": round(cost["modmul"] / (ms_step * 1e-3) / 1e12 / SHOUP_PEAK_T_PER_S, 3),
-            "ntt_butterflies_per_lt": butterflies, "ntt_ms_per_lt": round(ntt_ms, 4),
-            "ntt_T_butterflies_per_s": round(butterflies / (ntt_ms * 1e-3) / 1e12, 3),
-            "note": "modmul from the operation-count model (Table I conventions) over the whole step; peak from a "
-                    "multiply-add probe on this device"}
+    whole = {"compulsory_bytes_per_lt": comp, "ms_per_lt": round(ms_step, 4),
+             "GB_per_s": round(comp / (ms_step * 1e-3) / 1e9, 1),
+             "frac_of_hbm_peak": round(comp / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "hbm_floor_ms": round(comp / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+             "note": "keys + plaintexts + ciphertext in and out, each word once, over the measured step time"}
+    # The VALU side, from SQ counters of the same workload (profiles/): per
+    # kernel the share of the device's VALU issue slots it used and the share
+    # of its waves' lifetimes spent issuing VALU instructions or waiting.
+    valu = None
+    if valu_blk:
+        valu = {"source": os.path.relpath(PROFILE_VALU, ROOT),
+                "kernels": {k: {f: v[f] for f in ("valu_issue_frac", "valu_active_per_wave_cycle",
+                                                  "wait_per_wave_cycle", "valu_insts_per_wave")}
+                            for k, v in valu_blk["kernels"].items()
+                            if k.startswith(("ntt_pass", "bconv_kernel", "ks_", "mac_kernel"))}}
     out = {
         "metric": METRIC, "value": round(lt_s, 2), "unit": "LT/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -647,6 +806,7 @@ def main():
                                "split (4,4,4)", "N": prm.n, "level": level, "n_diag": 64, "split": list(th_split)},
         "effective_GB_per_s": round(comp * lt_s / 1e9, 1),
         "compulsory_bytes_per_lt": comp,
+        "whole_lt": whole,
         "plain_bsgs": {"split": list(bs_split), "ms_per_lt": round(bs_ms, 4), "lt_per_s": round(1e3 / bs_ms, 2),
                        "compulsory_bytes_per_lt": compulsory_bytes(prm, level, bs_split, "bsgs")},
         "th_vs_bsgs_speedup": round(bs_ms / ms_step, 3),
@@ -701,7 +861,9 @@ def main():
         out["serving_onfly"] = serving_leg(args.serve_seconds, args.serve_rate, torch, H, onfly=True)
         print("on-the-fly serving leg done", flush=True, file=sys.stderr)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prm, level, th_split)
+        specs_b = ragged_specs(prm, args.batch_items or 128, H)
+        serv = [(14 + g, lv) for _, g, lv, _, _ in serving_requests(10.0, 200.0)]
+        out["cpu_baseline"] = cpu_baseline(prm, level, th_split, H, specs_b, serv)
     print(json.dumps(out), flush=True)
 
 

@@ -63,7 +63,7 @@ def lib():
                      "orc_decompose", "orc_moddown", "orc_moddown_rescale", "orc_rescale", "orc_ks_inner",
                      "orc_p_scale", "orc_poly_from_signed", "orc_keygen_secret", "orc_get_secret",
                      "orc_gen_rotkey", "orc_encrypt", "orc_decrypt", "orc_rotate", "orc_lt_th",
-                     "orc_lt_bsgs", "orc_lt_naive"]:
+                     "orc_lt_bsgs", "orc_lt_naive", "orc_lt_dh"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -319,6 +319,24 @@ class Oracle:
         nk, r, kp = self._keys(keys)
         _check(lib().orc_lt_th(self.ctx, level, _p(ct[0]), _p(ct[1]), n1, n2, n3, ctypes.c_long(stride),
                                ctypes.c_long(centre), len(pts), _ptr_array(pts),
+                               nk, r, kp, _p(out[0]), _p(out[1])))
+        return out
+
+    def dh_plaintexts(self, diags, n1: int, n2: int, scale: float, stride: int = 1, centre: int = 0):
+        """Algorithm 1 input: f^_{n1 j + i} = phi_{-G_j}(f), G_j = stride (n1 j - centre), at PQ.
+        The same encodings as Algorithm 2's with an empty inner layer (n1' = 1)."""
+        return self.th_plaintexts(diags, 1, n1, n2, scale, stride, centre)
+
+    def lt_dh(self, level: int, ct: np.ndarray, split: Tuple[int, int], pts, keys, stride: int = 1,
+              centre: int = 0, combined: bool = True) -> np.ndarray:
+        """Double-hoisted BSGS (Algorithm 1), n1 baby and n2 giant steps."""
+        n1, n2 = split
+        ct = np.ascontiguousarray(ct, dtype=np.uint64)
+        out = np.empty((2, level, self.n), dtype=np.uint64)
+        pts = self._trunc(pts)
+        nk, r, kp = self._keys(keys)
+        _check(lib().orc_lt_dh(self.ctx, level, _p(ct[0]), _p(ct[1]), n1, n2, ctypes.c_long(stride),
+                               ctypes.c_long(centre), 1 if combined else 0, len(pts), _ptr_array(pts),
                                nk, r, kp, _p(out[0]), _p(out[1])))
         return out
 

@@ -570,6 +570,103 @@ void lt_th(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, in
 }
 
 // ---------------------------------------------------------------------------
+// Double-hoisted BSGS (Algorithm 1) with n1 baby steps and n2 giant steps,
+// written from the algorithm itself (not as Algorithm 2 with an empty inner
+// layer).  Inputs: keys swk~ for the baby rotations s*i (0 < i < n1) and the
+// giant rotations G_j = s*(n1 j - centre); plaintexts f^_{n1 j + i} =
+// phi_{-G_j}(f_{n1 j + i}) at PQ (K_max limbs, prefix-truncated).
+// Readings: the baby loop starts at i = 1, (a_0, b_0) being P c' itself,
+// and the giant block whose rotation vanishes is accumulated without key
+// switching (the j = 0 block of the plain algorithm); this gives the
+// algorithm's counts, n2 Decompose, n2 + 1 ModDown, n1 + n2 - 2 keys.  The
+// last line, ModDown of c0 and c1 followed by the rescale, is one ModDown by
+// P q_l when `combined` (the combination the paper applies to Algorithm 2's
+// last line), else ModDown and then eq. (1).  Absent diagonals are skipped:
+// a block without any contributes zero, a baby step no diagonal uses is
+// not computed.
+// ---------------------------------------------------------------------------
+void lt_dh(Ctx& c, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, Prog pg, const Diags& D,
+           const KeyMap& km, bool combined, uint64_t* o0, uint64_t* o1) {
+  const int n = c.n, K = c.K(level), beta = c.beta(level);
+  const size_t PL = (size_t)K * n;
+  const std::vector<int> PQ = pq_basis(c, level);
+  auto has = [&](int t) { return t < D.n && D.f[t] != nullptr; };
+  std::vector<char> baby(n1, 0);  // a_i, b_i feed some present diagonal
+  for (int j = 0; j < n2; ++j)
+    for (int i = 0; i < n1; ++i)
+      if (has(n1 * j + i)) baby[i] = 1;
+  bool any_baby = false;
+  for (int i = 1; i < n1; ++i) any_baby |= baby[i] != 0;
+  // Line 1: d = Decompose(c1').
+  Vec d((size_t)beta * PL);
+  if (any_baby) decompose(c, level, c1, d.data());
+  // Line 2: (a_0, b_0) = (P c0', P c1') mod PQ.
+  std::vector<Vec> A(n1), B(n1);
+  A[0].resize(PL);
+  B[0].resize(PL);
+  p_scale(c, level, c0, A[0].data());
+  p_scale(c, level, c1, B[0].data());
+  // Lines 3-5: a_i = phi_{s i}(a_0 + <d, swk~_{s i, 0}>), b_i = phi_{s i}(<d, swk~_{s i, 1}>).
+  for (int i = 1; i < n1; ++i) {
+    if (!baby[i]) continue;
+    const long r = pg.stride * i;
+    const uint64_t* key = need_key(c, km, r);
+    Vec x(PL), y(PL);
+    ks_inner(c, level, d.data(), key, x.data(), y.data());
+    add_inplace(c, PQ, x.data(), A[0].data());
+    A[i].resize(PL);
+    B[i].resize(PL);
+    automorph_ntt(c, r, x.data(), A[i].data(), K);
+    automorph_ntt(c, r, y.data(), B[i].data(), K);
+  }
+  // Line 6: (c0, c1) = (0, 0).
+  Vec C0(PL, 0), C1(PL, 0);
+  // Lines 7-12: giant steps.
+  for (int j = 0; j < n2; ++j) {
+    bool any = false;
+    for (int i = 0; i < n1; ++i) any |= has(n1 * j + i);
+    if (!any) continue;
+    // Line 8: (u0, u1) = sum_i (a_i, b_i) f^_{n1 j + i}.
+    Vec U0(PL, 0), U1(PL, 0);
+    for (int i = 0; i < n1; ++i) {
+      if (!has(n1 * j + i)) continue;
+      mac_inplace(c, PQ, U0.data(), A[i].data(), D.f[n1 * j + i]);
+      mac_inplace(c, PQ, U1.data(), B[i].data(), D.f[n1 * j + i]);
+    }
+    const long G = mod_slots(c, pg.stride * ((long)n1 * j - pg.centre));
+    if (G == 0) {  // no rotation: accumulated as is
+      add_inplace(c, PQ, C0.data(), U0.data());
+      add_inplace(c, PQ, C1.data(), U1.data());
+      continue;
+    }
+    // Lines 9-12: u1 = ModDown(u1); d = Decompose(u1);
+    // c0 += phi_G(u0 + <d, swk~_{G,0}>); c1 += phi_G(<d, swk~_{G,1}>).
+    Vec u1q((size_t)(level + 1) * n), dg((size_t)beta * PL);
+    moddown(c, level, U1.data(), u1q.data());
+    decompose(c, level, u1q.data(), dg.data());
+    const uint64_t* key = need_key(c, km, G);
+    Vec x(PL), y(PL), t(PL);
+    ks_inner(c, level, dg.data(), key, x.data(), y.data());
+    add_inplace(c, PQ, x.data(), U0.data());
+    automorph_ntt(c, G, x.data(), t.data(), K);
+    add_inplace(c, PQ, C0.data(), t.data());
+    automorph_ntt(c, G, y.data(), t.data(), K);
+    add_inplace(c, PQ, C1.data(), t.data());
+  }
+  // Line 13: ct = rescale(ModDown(c0), ModDown(c1)).
+  if (combined) {
+    moddown_rescale(c, level, C0.data(), o0);
+    moddown_rescale(c, level, C1.data(), o1);
+  } else {
+    Vec m0((size_t)(level + 1) * n), m1((size_t)(level + 1) * n);
+    moddown(c, level, C0.data(), m0.data());
+    moddown(c, level, C1.data(), m1.data());
+    rescale(c, level, m0.data(), o0);
+    rescale(c, level, m1.data(), o1);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Plain BSGS, eq. (5): f^_{n1 j + i} = phi_{-G_j}(f) at Q (L+1 limbs, prefix),
 // baby rotations s*i, giant rotations G_j = s*(n1 j - centre).
 // ---------------------------------------------------------------------------
@@ -840,6 +937,13 @@ int orc_lt_th(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n
               const uint64_t* const* keys, uint64_t* o0, uint64_t* o1) {
   ORC_TRY(lt_th(*as_ctx(cv), level, c0, c1, n1, n2, n3, Prog{stride, centre}, make_diags(nd, diags),
                 make_keys(nkeys, rots, keys), o0, o1))
+}
+
+int orc_lt_dh(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, long stride, long centre,
+              int combined, int nd, const uint64_t* const* diags, int nkeys, const long* rots,
+              const uint64_t* const* keys, uint64_t* o0, uint64_t* o1) {
+  ORC_TRY(lt_dh(*as_ctx(cv), level, c0, c1, n1, n2, Prog{stride, centre}, make_diags(nd, diags),
+                make_keys(nkeys, rots, keys), combined != 0, o0, o1))
 }
 
 int orc_lt_bsgs(void* cv, int level, const uint64_t* c0, const uint64_t* c1, int n1, int n2, long stride,

@@ -127,8 +127,10 @@ def _onfly_case(prm, o, keys, level, split, diags_by_t, v, seed, algo="th", stri
     ct = o.encrypt(level, v, delta, seed=seed)
     okeys = {r: keys[r] for r in rots}
     log("oracle LT", prm.log_n, algo, "level", level, "split", osplit, "diagonals", len(ts))
-    if algo in ("th", "dh"):
+    if algo == "th":
         ref = o.lt_th(level, ct, osplit, pts, okeys, stride=stride, centre=centre)
+    elif algo == "dh":  # the oracle's Algorithm 1
+        ref = o.lt_dh(level, ct, split, pts, okeys, stride=stride, centre=centre)
     elif algo == "bsgs":
         ref = o.lt_bsgs(level, ct, osplit, pts, okeys, stride=stride, centre=centre)
     else:

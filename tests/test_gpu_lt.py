@@ -81,18 +81,18 @@ def test_lt_errors(toy):
     assert e.value.code == H.CKKS_E_INVALID_ARG
 
 
-def test_dh_bsgs_is_th_with_unit_inner_layer(toy):
-    # CKKS_LT_DH_BSGS (n1, n2) == Algorithm 2 with (1, n1, n2), bit for bit.
+@pytest.mark.parametrize("split", [(4, 4), (2, 8), (8, 2)])
+def test_dh_bsgs_equals_algorithm1_oracle(toy, split):
+    # CKKS_LT_DH_BSGS (n1, n2) against the oracle's own Algorithm 1, bit for bit.
     import torch
     w = toy.w
     o = toy.o
-    split = (4, 4)
-    pts = o.th_plaintexts(w.diags, 1, *split, toy.delta)
+    pts = o.dh_plaintexts(w.diags, *split, toy.delta)
     keys = {r: k for r, k in toy.keys.items()}
     need = set(W.th_rotations(1, *split))
     for r in need - set(keys):
         keys[r] = o.rotkey(r)
-    ref = o.lt_th(w.level, toy.ct, (1,) + split, pts, keys)
+    ref = o.lt_dh(w.level, toy.ct, split, pts, keys)
     P = gpu_params(w.params)
     d = toy.device()
     dpts = [None if f is None else H.to_device(f) for f in pts]

@@ -65,8 +65,10 @@ def test_random_configurations_bit_exact():
         keys = {r: keycache[r] for r in rots}
         log("case", case, algo, split, "n", n, "stride", stride, "centre", centre, "level", level,
             "present", len(present))
-        if algo in ("th", "dh"):
+        if algo == "th":
             ref = o.lt_th(level, ct, th_split, pts, keys, stride=stride, centre=centre)
+        elif algo == "dh":  # the oracle's Algorithm 1
+            ref = o.lt_dh(level, ct, split, pts, keys, stride=stride, centre=centre)
         elif algo == "bsgs":
             ref = o.lt_bsgs(level, ct, split, pts, keys, stride=stride, centre=centre)
         else:

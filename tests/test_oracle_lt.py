@@ -134,16 +134,56 @@ def test_th_multi_digit_groups():
 
 
 @pytest.mark.parametrize("split", [(4, 4), (8, 2), (2, 8)])
-def test_dh_counts_table1(toy, split):
-    # Algorithm 1 (DH-BSGS) is Algorithm 2 with n1' = 1: Table I's DH row,
-    # n2 Decompose, n2 + 1 ModDown, n1 + n2 - 2 keys.
+def test_dh_algorithm1_counts_and_t4(toy, split):
+    # Algorithm 1 (DH-BSGS) as written in the oracle: Table I's DH row,
+    # n2 Decompose, n2 + 1 ModDown, n1 + n2 - 2 keys; T4 against M v.
     w, o, ct, keys, delta = toy
     n1, n2 = split
+    pts = o.dh_plaintexts(w.diags, n1, n2, delta)
     o.reset_counters()
-    out = o.lt_th(w.level, ct, (1, n1, n2), o.th_plaintexts(w.diags, 1, n1, n2, delta), keys)
+    out = o.lt_dh(w.level, ct, split, pts, keys)
     c = o.counters()
     assert c["decompose"] == n2 and c["moddown"] == n2 + 1 and c["keys"] == n1 + n2 - 2
     assert np.abs(_decode(o, out, w, delta) - W.matvec(w.diags, w.vector)).max() <= 5e-3
+
+
+@pytest.mark.parametrize("split,prog", [((4, 4), (1, 0)), ((8, 2), (1, 0)), ((2, 8), (1, 0)), ((4, 4), (3, 8)),
+                                        ((2, 8), (5, 3))])
+def test_dh_algorithm1_equals_algorithm2_with_unit_inner_layer(toy, split, prog):
+    # Two separately written algorithms reach the same bytes: Algorithm 1
+    # with (n1, n2) and Algorithm 2 with (n1', n2', n3') = (1, n1, n2) take
+    # the same steps on the same operands (Section III), so any slip in
+    # either one's indexing, rotation or accumulation shows here.
+    w, o, ct, keys, delta = toy
+    n1, n2 = split
+    s, c = prog
+    rots = set(W.th_rotations(1, n1, n2, stride=s, centre=c, slots=w.params.slots))
+    ks = {r: keys[r] if r in keys else o.rotkey(r) for r in rots}
+    diags = {d: w.diags[d] for d in w.diags}
+    # a progression offset s (t - c): place the workload's diagonals there
+    if prog != (1, 0):
+        S = w.params.slots
+        diags = {(s * (t - c)) % S: w.diags[t % 16] for t in range(n1 * n2) if t % 3 != 1}
+    pts = o.dh_plaintexts(diags, n1, n2, delta, stride=s, centre=c)
+    dh = o.lt_dh(w.level, ct, split, pts, ks, stride=s, centre=c)
+    th = o.lt_th(w.level, ct, (1, n1, n2), o.th_plaintexts(diags, 1, n1, n2, delta, stride=s, centre=c), ks,
+                 stride=s, centre=c)
+    assert np.array_equal(dh, th)
+    assert np.abs(_decode(o, dh, w, delta) - W.matvec(diags, w.vector)).max() <= 5e-3
+
+
+def test_dh_algorithm1_sequential_last_line(toy):
+    # The last line read literally (ModDown of c0 and c1, then eq. (1))
+    # against the combined ModDown by P q_l: different floors, the same
+    # message within the rounding error.
+    w, o, ct, keys, delta = toy
+    pts = o.dh_plaintexts(w.diags, 4, 4, delta)
+    comb = o.lt_dh(w.level, ct, (4, 4), pts, keys)
+    seq = o.lt_dh(w.level, ct, (4, 4), pts, keys, combined=False)
+    assert not np.array_equal(comb, seq)
+    za, zb = _decode(o, comb, w, delta), _decode(o, seq, w, delta)
+    assert np.abs(za - zb).max() <= 5e-3
+    assert np.abs(zb - W.matvec(w.diags, w.vector)).max() <= 5e-3
 
 
 def test_paper_set_parameters_are_valid():
