@@ -30,14 +30,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CKKS LT evals/s and HBM GB/s at N=2^16, 64 diags; batched vs plain BSGS"
 HBM_PEAK_GBS = 8000.0
-# rocprofv3 summaries of `bench.py --profile-only` (TH-BSGS (4,4,4) and plain
-# BSGS (8,8) at N=2^16, level 24, 64 diagonals), written by
+# rocprofv3 summaries of `bench.py --profile-only --only th` (TH-BSGS (4,4,4)
+# at N=2^16, level 24, 64 diagonals), written by
 # paper_2605_17222_amd.profiling; their figures are used only while the
 # library's sources are the ones that were profiled.
 PROFILES = os.path.join(ROOT, "profiles")
-PROFILE_TRACE = os.path.join(PROFILES, "kernel_trace_th444_bsgs88_n16_l24_d64.md")
-PROFILE_HBM = os.path.join(PROFILES, "hbm_counters_th444_bsgs88_n16_l24_d64.md")
-PROFILE_VALU = os.path.join(PROFILES, "valu_counters_th444_bsgs88_n16_l24_d64.md")
+PROFILE_TRACE = os.path.join(PROFILES, "kernel_trace_th444_n16_l24_d64.md")
+PROFILE_HBM = os.path.join(PROFILES, "hbm_counters_th444_n16_l24_d64.md")
+PROFILE_VALU = os.path.join(PROFILES, "valu_counters_th444_n16_l24_d64.md")
+PROFILE_LTS = 12  # TH-BSGS LTs in those runs: `--profile-only --only th --steps 2 --warmup 10`
 # The kernel (and template instance) behind each timed kernel id in one
 # TH-BSGS (4,4,4) step at level 24, as rocprofv3 names it.
 TH444_KERNEL = {"ptmac": "mac_kernel<4, false>", "keyswitch_gather": "ks_gather_kernel<false, 3>"}
@@ -53,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-case", default=None, help=argparse.SUPPRESS)  # one oracle timing, JSON (child process)
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baseline (for rocprofv3)")
+    ap.add_argument("--only", choices=("th", "bsgs", "both"), default="both",
+                    help="with --profile-only: which single-LT workload runs (TH-BSGS (4,4,4), plain BSGS (8,8))")
     ap.add_argument("--packed", action="store_true",
                     help="with --profile-only: keys and TH-BSGS plaintexts in the packed layout")
     ap.add_argument("--batch-items", type=int, default=128, help="ragged batch size (0: skip)")
@@ -99,7 +102,9 @@ def events_ms(torch, stream, fn, reps):
 
 def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True, packed=False):
     """Uniform residues on the device for the ciphertext, keys and plaintexts
-    (packed: keys and TH-BSGS plaintexts in the packed resident layout)."""
+    (packed: keys and TH-BSGS plaintexts in the packed resident layout).  The
+    keys are views into one allocation, and so are the plaintexts (a resident
+    key set and matrix, not hundreds of separate buffers)."""
     import workload as W
     n = prm.n
     pq = list(prm.p) + list(prm.q)
@@ -108,8 +113,12 @@ def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True, packe
 
     def residues(moduli_rows):
         m = torch.tensor(moduli_rows, dtype=torch.int64, device="cuda").view(-1, 1)
-        x = torch.randint(0, 2 ** 62, (len(moduli_rows), n), generator=g, dtype=torch.int64, device="cuda")
-        return torch.remainder(x, m)
+        x = torch.empty((len(moduli_rows), n), dtype=torch.int64, device="cuda")
+        for r0 in range(0, len(moduli_rows), 1024):  # bounded temporaries
+            r1 = min(len(moduli_rows), r0 + 1024)
+            torch.randint(0, 2 ** 62, (r1 - r0, n), generator=g, dtype=torch.int64, device="cuda", out=x[r0:r1])
+            torch.remainder(x[r0:r1], m[r0:r1], out=x[r0:r1])
+        return x
 
     qmods = [prm.q[j] for j in range(level + 1)]
     c0, c1 = residues(qmods), residues(qmods)
@@ -123,10 +132,13 @@ def make_inputs(P, prm, level, split, algo, seed, torch, H, with_pts=True, packe
         rots = W.bsgs_rotations(*split)
         pt_mods = list(prm.q)
         n_pt = split[0] * split[1]
-    keys = {}
-    for r in rots:
-        keys[r] = residues(pq[:kmax] * (2 * beta_max)).view(beta_max, 2, kmax, n)
-    pts = [residues(pt_mods) for _ in range(n_pt)] if with_pts else []
+    per_key = pq[:kmax] * (2 * beta_max)
+    kall = residues(per_key * len(rots))
+    keys = {r: kall[i * len(per_key):(i + 1) * len(per_key)].view(beta_max, 2, kmax, n) for i, r in enumerate(rots)}
+    pts = []
+    if with_pts:
+        pall = residues(pt_mods * n_pt)
+        pts = [pall[t * len(pt_mods):(t + 1) * len(pt_mods)] for t in range(n_pt)]
     if packed:
         keys = {r: H.ckks_pack(P, k) for r, k in keys.items()}
         if algo == "th":
@@ -470,11 +482,14 @@ def serving_requests(seconds, rate, seed=2024):
 SERVING_SPLIT = (4, 16, 4)
 
 
-def batched_leg(P, prm, items, steps, torch, H, seed=77, chunk=32):
+def batched_leg(P, prm, items, steps, torch, H, seed=77):
     """Ragged batch: `items` ciphertexts, level ~ U{8..24}, diagonal count ~
     U{16, 32, 64, 128} (banded), each with its own plaintexts and an
-    autotuned TH split; keys shared.  A step evaluates every item, `chunk`
-    items per ckks_lt_eval_batch call (the calls share one workspace)."""
+    autotuned TH split; keys shared.  A step is one ckks_lt_eval_batch call
+    over every item (all of Algorithm 2's lines issued for the whole batch in
+    lockstep), timed eagerly and replayed from a HIP graph captured once; if
+    the batch's workspace does not fit next to the resident plaintexts, the
+    items are split over calls of 32."""
     import workload as W
     residues = residue_maker(prm.n, torch, seed)
     pq = list(prm.p) + list(prm.q)
@@ -490,25 +505,44 @@ def batched_leg(P, prm, items, steps, torch, H, seed=77, chunk=32):
         pt_bytes += nd * K * prm.n * 8
         batch.append(H.BatchItem(level, delta, residues(qm), residues(qm), sp, pts, delta, keys,
                                  H.empty((level, prm.n)), H.empty((level, prm.n))))
+    free, _ = torch.cuda.mem_get_info()
+    chunk = items
+    wsb = H.ckks_lt_batch_workspace_size(P, batch, H.CKKS_LT_TH_BSGS)
+    if wsb > 0.9 * free:
+        chunk = 32
     chunks = [batch[i:i + chunk] for i in range(0, len(batch), chunk)]
     wsb = max(H.ckks_lt_batch_workspace_size(P, c, H.CKKS_LT_TH_BSGS) for c in chunks)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step():
+    def run(st):
         for c in chunks:
-            code = H.ckks_lt_eval_batch(P, c, H.CKKS_LT_TH_BSGS, ws, wsb, stream)
+            code = H.ckks_lt_eval_batch(P, c, H.CKKS_LT_TH_BSGS, ws, wsb, st)
             assert code == H.CKKS_OK, H.strerror(code)
 
-    step()
-    ms, wall = events_ms(torch, stream, step, steps)
+    run(stream)
+    ms, wall = events_ms(torch, stream, lambda: run(stream), steps)
+    # the whole step captured once into a HIP graph and replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            run(torch.cuda.current_stream())
+    stream.wait_stream(side)
+    g.replay()
+    ms_g, wall_g = events_ms(torch, stream, g.replay, steps)
     levels = [sp[0] for sp in specs]
     res = {"items": items, "items_per_call": chunk, "steps": steps, "ms_per_batch": round(ms / steps, 3),
-           "lt_per_s": round(items * steps / wall, 1), "workspace_bytes": wsb, "resident_pt_bytes": pt_bytes,
-           "keys": len(rots), "levels": [min(levels), max(levels)],
+           "lt_per_s": round(items * steps / wall, 1), "graph_ms_per_batch": round(ms_g / steps, 3),
+           "graph_lt_per_s": round(items * steps / wall_g, 1), "workspace_bytes": wsb,
+           "resident_pt_bytes": pt_bytes, "keys": len(rots), "levels": [min(levels), max(levels)],
            "splits": sorted(set("%dx%dx%d" % sp for _, _, sp in specs)),
+           "compulsory_bytes": pt_bytes + len(rots) * 2 * 3 * (prm.alpha + prm.max_level + 1) * prm.n * 8 +
+           sum(2 * (2 * lv + 1) * prm.n * 8 for lv, _, _ in specs),
            "recipe": "level ~ U{8..24}, n ~ U{16,32,64,128} banded, autotuned TH splits, shared keys, seed %d" % seed}
-    del batch, keys, ws
+    res["effective_GB_per_s"] = round(res["compulsory_bytes"] / (ms_g / steps * 1e-3) / 1e9, 1)
+    del batch, keys, ws, g
     torch.cuda.empty_cache()
     return res
 
@@ -716,9 +750,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        time_lt(P, prm, level, th_split, "th", max(1, args.steps), args.warmup, torch, H, packed=args.packed)
-        time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), args.warmup, torch, H, packed=args.packed)
-        print("profile run done", flush=True)
+        if args.only in ("th", "both"):
+            time_lt(P, prm, level, th_split, "th", max(1, args.steps), args.warmup, torch, H, packed=args.packed)
+        if args.only in ("bsgs", "both"):
+            time_lt(P, prm, level, bs_split, "bsgs", max(1, args.steps), args.warmup, torch, H, packed=args.packed)
+        print("profile run done: %d LTs per algorithm" % (max(1, args.steps) + args.warmup), flush=True)
         return
 
     all_mask = (1 << len(H.KERNELS)) - 1
@@ -788,6 +824,28 @@ def main():
              "frac_of_hbm_peak": round(comp / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
              "hbm_floor_ms": round(comp / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
              "note": "keys + plaintexts + ciphertext in and out, each word once, over the measured step time"}
+    # The paper's off-chip traffic model (Table III) for this split, with the
+    # reuse this library's kernels get on chip as its parallelism (all limbs
+    # of a polynomial per kernel, up to 8 keys x 8 digit sets per key-switch
+    # launch, the n3 accumulators of the multiply-accumulate in registers),
+    # against the HBM bytes the counters measured per LT and the step time
+    n1s, n2s, n3s = th_split
+    par = dict(m1=1, l1=level + 1, m2=max(1, n1s - 1), l2=K, m3=min(8, max(1, n2s - 1)), m4=min(8, n1s), l3=K,
+               m5=min(8, n3s), l4=K, m6=max(1, n3s - 1), l5=K)
+    tm = H.ckks_th_traffic_model(prm.log_n, level, prm.alpha, th_split, 64, 64, par)
+    measured = None
+    if hbm:
+        measured = sum(v["hbm_bytes"] * v["dispatches"] for k, v in hbm["kernels"].items()
+                       if not k.startswith("at::")) / PROFILE_LTS
+    paper_model = {
+        "parallelism": par, "predicted_bytes_per_lt": tm["total_bytes"],
+        "predicted_ms_at_hbm_peak": round(tm["total_bytes"] / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+        "measured_hbm_bytes_per_lt": measured,
+        "measured_over_predicted_bytes": round(measured / tm["total_bytes"], 3) if measured else None,
+        "measured_ms_per_lt": round(ms_step, 4),
+        "library_model_predicted_ms": round(H.ckks_lt_predict(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS,
+                                                              th_split, 64) * 1e3, 4),
+        "note": "Table III's phases priced for this schedule; its on-chip reuse stands in for the FPGA buffers"}
     # The VALU side, from SQ counters of the same workload (profiles/): per
     # kernel the share of the device's VALU issue slots it used and the share
     # of its waves' lifetimes spent issuing VALU instructions or waiting.
@@ -807,6 +865,7 @@ def main():
         "effective_GB_per_s": round(comp * lt_s / 1e9, 1),
         "compulsory_bytes_per_lt": comp,
         "whole_lt": whole,
+        "paper_traffic_model": paper_model,
         "plain_bsgs": {"split": list(bs_split), "ms_per_lt": round(bs_ms, 4), "lt_per_s": round(1e3 / bs_ms, 2),
                        "compulsory_bytes_per_lt": compulsory_bytes(prm, level, bs_split, "bsgs")},
         "th_vs_bsgs_speedup": round(bs_ms / ms_step, 3),

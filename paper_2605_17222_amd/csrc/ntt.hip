@@ -304,6 +304,11 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
     ntt_body<PLOG, G, COL, FWD, false, SIN>(R, limb, pr, log_n, epi, lds);
 }
 
+// Sub-transforms per workgroup: 4096 / P (16 at N = 2^16: 256 threads,
+// 128-byte column segments).  A quarter of that for launches over a few
+// limbs (4x the workgroups) was measured slower: the inverse column pass
+// over 9-10 limbs 0.106 -> 0.147 ms per (4,4,4) LT, its 32-byte column
+// segments costing more than the extra workgroups gain.
 template <int PLOG, bool COL, bool FWD>
 hipError_t launch_pass(const ckks_params* P, const NttArgs& a, int total, int epi, hipStream_t s) {
   constexpr int Pn = 1 << PLOG;

@@ -102,3 +102,55 @@ def test_serving_burst_of_16_equals_alone():
         it = H.BatchItem(level, delta, cts[ci][0], cts[ci][1], split, pool[:nd], delta, keys, o0, o1)
         a0, a1 = _alone(P, it, torch)
         assert np.array_equal(a0, H.to_host(o0)) and np.array_equal(a1, H.to_host(o1)), (g, level, nd)
+
+
+def test_ragged_batch_of_128_in_one_graph_equals_alone():
+    # The batched benchmark's step: all 128 ragged items in one
+    # ckks_lt_eval_batch call, captured once into a HIP graph.  Every replay
+    # (outputs cleared eagerly in between) must give each sampled item the
+    # bytes of its evaluation alone.
+    import torch
+    prm = W.params_n16()
+    P = gpu_params(prm)
+    specs = B.ragged_specs(prm, 128, H)
+    residues = B.residue_maker(prm.n, torch, 77)
+    pq = list(prm.p) + list(prm.q)
+    keys = B.device_keys(prm, sorted(set().union(*[W.th_rotations(*sp) for _, _, sp in specs])), residues)
+    delta = 2.0 ** prm.log_delta
+    batch = []
+    for level, nd, sp in specs:
+        K = prm.alpha + level + 1
+        qm = [prm.q[j] for j in range(level + 1)]
+        pts = [residues(pq[:K]) for _ in range(nd)]
+        batch.append(H.BatchItem(level, delta, residues(qm), residues(qm), sp, pts, delta, keys,
+                                 H.empty((level, prm.n)), H.empty((level, prm.n))))
+    wsb = H.ckks_lt_batch_workspace_size(P, batch, H.CKKS_LT_TH_BSGS)
+    log("batch of 128, workspace", wsb)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            code = H.ckks_lt_eval_batch(P, batch, H.CKKS_LT_TH_BSGS, ws, wsb, torch.cuda.current_stream())
+    assert code == H.CKKS_OK, H.strerror(code)
+    torch.cuda.synchronize()
+    sample = [int(t) for t in np.random.Generator(np.random.PCG64(79)).choice(128, size=6, replace=False)]
+    ref = {}
+    for rep in range(3):
+        for it in batch:
+            it.out0.zero_()
+            it.out1.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        log("replay", rep)
+        for t in sample:
+            it = batch[t]
+            assert it.status == H.CKKS_OK
+            got = (H.to_host(it.out0), H.to_host(it.out1))
+            if t not in ref:
+                ref[t] = _alone(P, it, torch)
+            assert np.array_equal(got[0], ref[t][0]) and np.array_equal(got[1], ref[t][1]), (rep, t, specs[t])
+    del g, ws
+    torch.cuda.empty_cache()
