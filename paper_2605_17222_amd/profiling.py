@@ -84,18 +84,21 @@ def read_counters(d: str) -> Dict[str, dict]:
         key = (short_name(r["Kernel_Name"]), r["Dispatch_Id"])
         per[key][r["Counter_Name"]] += float(r["Counter_Value"])
         meta[key] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-    out = collections.defaultdict(lambda: {"dispatches": 0, "counters": collections.defaultdict(float), "us": 0.0})
+    out = collections.defaultdict(lambda: {"dispatches": 0, "counters": collections.defaultdict(float), "us": 0.0,
+                                           "max": collections.defaultdict(float)})
     for (k, _), cs in per.items():
         o = out[k]
         o["dispatches"] += 1
         for c, v in cs.items():
             o["counters"][c] += v
+            o["max"][c] = max(o["max"][c], v)
     for (k, disp), us in meta.items():
         out[k]["us"] += us
     res = {}
     for k, o in out.items():
         n = o["dispatches"]
-        res[k] = {"dispatches": n, "us": o["us"] / n, "counters": {c: v / n for c, v in o["counters"].items()}}
+        res[k] = {"dispatches": n, "us": o["us"] / n, "counters": {c: v / n for c, v in o["counters"].items()},
+                  "max": dict(o["max"])}
     return res
 
 
@@ -104,7 +107,7 @@ def _largest_copy(cnt: Dict[str, dict], counter: str) -> float:
     rows = [v for k, v in cnt.items() if k.startswith(COPY_KERNEL)]
     if not rows:
         raise RuntimeError("no %s dispatch to calibrate %s" % (COPY_KERNEL, counter))
-    return max(v["counters"].get(counter, 0.0) for v in rows)
+    return max(v["max"].get(counter, 0.0) for v in rows)
 
 
 def read_block(path: str) -> Optional[dict]:

@@ -234,3 +234,27 @@ def test_paper_set_a_oracle_t3_t4():
         assert np.all(e <= bound)
         assert np.median(e) <= 3e-5
     assert np.all(np.abs(zt - zb) <= 2 * bound)
+
+
+def test_paper_set_a_plaintext_scale_q_l_uniform_1e4():
+    # Set-A with the plaintext scale taken from the set's own primes: Delta_pt
+    # = q_l, the prime the LT's last line divides by, so the output scale is
+    # the input's Delta = 2^40 again (not 2^80 / q_l ~ 2^26).  The floor bias
+    # of eq. (1)/(4) then sits 2^14 times lower relative to the message and
+    # T4 holds at 1e-4 in every slot, slot 0 included.
+    prm = W.params_paper_set("A")
+    o = O.Oracle(prm)
+    o.keygen(181)
+    S, delta = prm.slots, 2.0 ** prm.log_delta
+    diags = W.banded_diagonals(182, S, range(32))
+    v = W.input_vector(183, S)
+    level = prm.max_level
+    pt_scale = float(prm.q[level])
+    ct = o.encrypt(level, v, delta, seed=184)
+    keys = o.rotkeys(sorted(set(W.th_rotations(2, 4, 4)) | set(W.bsgs_rotations(4, 8))))
+    th = o.lt_th(level, ct, (2, 4, 4), o.th_plaintexts(diags, 2, 4, 4, pt_scale), keys)
+    bs = o.lt_bsgs(level, ct, (4, 8), o.bsgs_plaintexts(diags, 4, 8, pt_scale), keys)
+    scale = delta * pt_scale / prm.q[level]
+    ref = W.matvec(diags, v)
+    for out in (th, bs):
+        assert np.abs(o.decrypt_slots(out, scale) - ref).max() <= 1e-4
