@@ -245,6 +245,7 @@ def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0,
     for _ in range(steps):
         step()
     ev1.record(stream)
+    enqueue_ms = (time.perf_counter() - t0) * 1e3  # host time to enqueue the steps
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_events = ev0.elapsed_time(ev1)
@@ -254,7 +255,7 @@ def time_lt(P, prm, level, split, algo, steps, warmup, torch, H, profile_mask=0,
             if profile_mask & (1 << k):
                 prof[name] = H.ckks_profile_read(k)
         H.ckks_profile_enable(0)
-    return wall, ms_events, prof, ws_bytes
+    return wall, ms_events, prof, ws_bytes, enqueue_ms
 
 
 # The paper's FPGA latency for its dense LTs (Table VIII, its design, Set-A/B/C): context
@@ -760,22 +761,22 @@ def main():
     all_mask = (1 << len(H.KERNELS)) - 1
     # 1) a short pass with every kernel timed, to find the dominant kernel
     probe_steps = 3
-    _, ms_probe, prof, ws_bytes = time_lt(P, prm, level, th_split, "th", probe_steps, args.warmup, torch, H, all_mask)
+    _, ms_probe, prof, ws_bytes, _ = time_lt(P, prm, level, th_split, "th", probe_steps, args.warmup, torch, H, all_mask)
     dom = max(prof, key=lambda k: prof[k][1])
     dom_id = H.KERNELS.index(dom)
     # 2) the timed region: K steps, HIP events around the dominant kernel only
-    wall, ms_ev, prof_dom, _ = time_lt(P, prm, level, th_split, "th", args.steps, args.warmup, torch, H, 1 << dom_id)
+    wall, ms_ev, prof_dom, _, enq_main = time_lt(P, prm, level, th_split, "th", args.steps, args.warmup, torch, H, 1 << dom_id)
     ms_step = ms_ev / args.steps
     lt_s = args.steps / wall
     # 3) plain BSGS beside it
     bs_steps = max(3, args.steps // 2)
-    wall_b, ms_ev_b, _, _ = time_lt(P, prm, level, bs_split, "bsgs", bs_steps, args.warmup, torch, H)
+    wall_b, ms_ev_b, _, _, _ = time_lt(P, prm, level, bs_split, "bsgs", bs_steps, args.warmup, torch, H)
     bs_ms = ms_ev_b / bs_steps
 
     n_l, ms_l, bytes_l = prof_dom[dom]
     avg_s = ms_l / n_l * 1e-3
     K = prm.alpha + level + 1
-    # Section 8(d)'s algorithmic unit of the dominant kernel: for the
+    # The algorithmic unit of the dominant kernel: for the
     # plaintext multiply-accumulate, the plaintexts it streams (17 MiB per
     # diagonal: K limbs of N words), every present diagonal of the step read
     # once; for other kernels, each input and output word once (the library's
@@ -873,21 +874,23 @@ def main():
         "roofline": roofline,
         "valu": valu,
         "kernels": breakdown,
+        "host_enqueue_ms_per_step": round(enq_main / args.steps, 4),
         "step_ms": step_percentiles(P, prm, level, th_split, 100, torch, H, args.warmup),
     }
     # the split the library's autotuner picks for this workload, timed the same way
     at_split, at_pred = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, 64)
     at_split = tuple(at_split)
-    wall_a, ms_a, _, _ = time_lt(P, prm, level, at_split, "th", args.steps, args.warmup, torch, H)
+    wall_a, ms_a, _, _, enq_a = time_lt(P, prm, level, at_split, "th", args.steps, args.warmup, torch, H)
     out["autotuned_split"] = {"split": list(at_split), "predicted_ms": round(at_pred * 1e3, 4),
                               "ms_per_lt": round(ms_a / args.steps, 4), "lt_per_s": round(args.steps / wall_a, 2),
+                              "host_enqueue_ms_per_lt": round(enq_a / args.steps, 4),
                               "compulsory_bytes_per_lt": compulsory_bytes(prm, level, at_split, "th")}
     # the same LTs with keys and TH-BSGS plaintexts resident in the packed
     # layout (limbs of the 40-bit primes in 5 bytes per coefficient): bit-
     # identical results, fewer bytes for the key-switch and MAC kernels
     packed = {}
     for name, split, algo in (("th", th_split, "th"), ("th_autotuned", at_split, "th"), ("plain_bsgs", bs_split, "bsgs")):
-        wall_p, ms_p, _, _ = time_lt(P, prm, level, split, algo, args.steps, args.warmup, torch, H, packed=True)
+        wall_p, ms_p, _, _, _ = time_lt(P, prm, level, split, algo, args.steps, args.warmup, torch, H, packed=True)
         packed[name] = {"split": list(split), "ms_per_lt": round(ms_p / args.steps, 4),
                         "lt_per_s": round(args.steps / wall_p, 2)}
     packed["packed_poly_bytes"] = H.ckks_packed_poly_bytes(P)

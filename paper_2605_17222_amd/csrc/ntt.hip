@@ -51,7 +51,7 @@ __device__ __forceinline__ uint64_t as_u(double d) { return (uint64_t)__double_a
 // coefficients (LimbRange::signed_in).
 template <int PLOG, int G, bool COL, bool FWD, bool FP, bool SIN>
 __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const PrimeDev& pr, int log_n, int epi,
-                                         uint64_t* lds) {
+                                         uint64_t* lds, double* tws) {
   constexpr int P = 1 << PLOG;
   constexpr int T = P / 16;           // threads per sub-transform
   constexpr int RS = P + P / 16 + 1;  // LDS row stride (padded)
@@ -80,13 +80,21 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
   uint64_t v[16];  // integer residues, or double bits on the FP path
   auto addr = [&](int x) -> size_t { return COL ? (size_t)x * ncols + sub : (size_t)sub * P + x; };
 
-  // FP row pass: the factor tables of this direction and this row.
-  const double* __restrict__ tg = nullptr;
-  const double* __restrict__ tr = nullptr;
-  if (FP && !COL) {
-    tg = pr.trow + (FWD ? 0 : ntt_row_tables_size(log_n));
-    tr = tg + P + 2 * (size_t)sub * PLOG;
-  }
+  // FP row pass: the factor tables of this direction, G (P doubles, shared
+  // by every row) and the R factors of the workgroup's G rows, staged into
+  // LDS once (stage_tw) so that no stage waits on a global load for its
+  // twiddles.
+  const double* tg = tws;
+  const double* tr = tws + P + 2 * g * PLOG;
+  auto stage_tw = [&]() {
+    if (FP && !COL) {
+      const double* __restrict__ gs = pr.trow + (FWD ? 0 : ntt_row_tables_size(log_n));
+      const double* __restrict__ rs = gs + P + 2 * (size_t)(blockIdx.x * G) * PLOG;
+      for (int e = tid; e < P; e += G * P / 16) tws[e] = gs[e];
+      for (int e = tid; e < G * 2 * PLOG; e += G * P / 16) tws[P + e] = rs[e];
+      __syncthreads();
+    }
+  };
   // Twiddle of stage s, group y (index base 2^s + y): the value and its
   // companion (Shoup word, or w/q on the FP path), as raw 64-bit words.
   auto twid = [&](int s, uint32_t y, uint64_t& w, uint64_t& wp) {
@@ -210,6 +218,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
 #pragma unroll
       for (int u = 0; u < 16; ++u) v[u] = __builtin_nontemporal_load(src + addr(j + T * u));
     }
+    if (!COL) stage_tw();
     if (first) convert_in();
     round1();
     recentre();
@@ -252,6 +261,7 @@ __device__ __forceinline__ void ntt_body(const LimbRange& R, int limb, const Pri
 #pragma unroll
         for (int u = 0; u < 16; ++u) cp[addr(j + T * u)] = v[u];
       }
+      stage_tw();
       to_lds(true);
       __syncthreads();
       from_lds(false);
@@ -289,6 +299,7 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
   constexpr int P = 1 << PLOG;
   constexpr int RS = P + P / 16 + 1;
   __shared__ uint64_t lds[G * RS];
+  __shared__ double tws[COL ? 1 : P + G * 2 * PLOG];  // FP row pass twiddle factors
   // Which limb (uniform over the workgroup).
   int limb = blockIdx.y;
   int ri = 0;
@@ -299,9 +310,9 @@ __global__ void __launch_bounds__(G*(1 << PLOG) / 16)
   const LimbRange& R = args.r[ri];
   const PrimeDev& pr = primes[R.prime0 + limb];
   if (pr.fp)
-    ntt_body<PLOG, G, COL, FWD, true, SIN>(R, limb, pr, log_n, epi, lds);
+    ntt_body<PLOG, G, COL, FWD, true, SIN>(R, limb, pr, log_n, epi, lds, tws);
   else
-    ntt_body<PLOG, G, COL, FWD, false, SIN>(R, limb, pr, log_n, epi, lds);
+    ntt_body<PLOG, G, COL, FWD, false, SIN>(R, limb, pr, log_n, epi, lds, tws);
 }
 
 // Sub-transforms per workgroup: 4096 / P (16 at N = 2^16: 256 threads,

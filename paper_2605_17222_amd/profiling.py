@@ -142,7 +142,7 @@ def _write(path: str, title: str, cmds, intro: str, table, block: dict, notes: s
         f.write("\n".join(lines))
 
 
-def write_trace(d: str, out: str, cmd: str, title: str):
+def write_trace(d: str, out: str, cmd: str, title: str, intro: str = ""):
     tr = read_trace(d)
     total = sum(v["total_us"] for v in tr.values())
     table = ["| Kernel | Calls | Total ms | Avg us | % |", "|---|---|---|---|---|"]
@@ -151,7 +151,7 @@ def write_trace(d: str, out: str, cmd: str, title: str):
                                                              100 * v["total_us"] / total))
     block = {"sources_digest": sources_digest(), "kernels": {k: {"calls": v["calls"], "avg_us": round(v["avg_us"], 3)}
                                                              for k, v in tr.items()}}
-    _write(out, title, [cmd], "", table, block)
+    _write(out, title, [cmd], intro, table, block)
 
 
 def write_hbm(fetch_dir: str, write_dir: str, out: str, cmds, title: str):
@@ -233,6 +233,7 @@ def main():
     a.add_argument("--out", required=True)
     a.add_argument("--cmd", required=True)
     a.add_argument("--title", required=True)
+    a.add_argument("--intro", default="")
     b = sub.add_parser("hbm")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -247,7 +248,7 @@ def main():
     c.add_argument("--title", required=True)
     args = ap.parse_args()
     if args.what == "trace":
-        write_trace(args.dir, args.out, args.cmd, args.title)
+        write_trace(args.dir, args.out, args.cmd, args.title, args.intro)
     elif args.what == "hbm":
         write_hbm(args.fetch, args.write, args.out, args.cmd, args.title)
     else:
