@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="Poisson serving run length (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--no-chain", action="store_true", help="skip the DFT-like chain")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the split sweep (two cost models against time)")
     ap.add_argument("--dense-steps", type=int, default=2,
                     help="timed steps of the dense n = N/2 LT with on-the-fly plaintexts (0: skip)")
     ap.add_argument("--dense-only", action="store_true",
@@ -588,6 +589,76 @@ def same_shape_batch_leg(P, prm, level, split, items, steps, torch, H):
             "graph_ms_per_batch": round(ms_g / steps, 3), "graph_lt_per_s": round(items * steps / wall_g, 1)}
 
 
+# TH splits of 64-80 diagonals timed by the sweep: every (n1, n2, n3) with
+# n1 n2 n3 = 64 and each factor in {1, 2, 4, 8, 16, 32} that the two models
+# rank differently, plus the cube.
+SWEEP_SPLITS = ((1, 16, 4), (2, 8, 4), (4, 4, 4), (2, 16, 2), (4, 8, 2), (1, 8, 8), (1, 32, 2), (2, 4, 8),
+                (4, 2, 8), (8, 2, 4), (4, 16, 1), (8, 4, 2), (2, 32, 1), (8, 8, 1), (1, 4, 16), (2, 2, 16))
+
+
+def paper_parallelism(level, K, split):
+    """Table III's on-chip parallelism mapped onto this library's schedule:
+    all limbs of a polynomial per kernel, up to 8 keys x 8 digit sets per
+    key-switch launch, the n3 accumulators of the multiply-accumulate in
+    registers."""
+    n1, n2, n3 = split
+    return dict(m1=1, l1=level + 1, m2=max(1, n1 - 1), l2=K, m3=min(8, max(1, n2 - 1)), m4=min(8, n1), l3=K,
+                m5=min(8, n3), l4=K, m6=max(1, n3 - 1), l5=K)
+
+
+def _ranks(xs):
+    order = sorted(range(len(xs)), key=lambda i: xs[i])
+    r = [0] * len(xs)
+    for pos, i in enumerate(order):
+        r[i] = pos
+    return r
+
+
+def _spearman(a, b):
+    ra, rb = _ranks(a), _ranks(b)
+    n = len(a)
+    return 1 - 6 * sum((x - y) ** 2 for x, y in zip(ra, rb)) / (n * (n * n - 1))
+
+
+def split_sweep_leg(P, prm, level, steps, warmup, torch, H):
+    """Every split of SWEEP_SPLITS timed (events over `steps` LTs after
+    `warmup`), priced by the library's predictor (ckks_lt_predict) and by the
+    paper's off-chip traffic model (Table III, bytes per LT) turned into time
+    by one bandwidth fitted over the sweep (least squares through 0)."""
+    K = prm.alpha + level + 1
+    rows = []
+    for split in SWEEP_SPLITS:
+        _, ms, _, _, _ = time_lt(P, prm, level, split, "th", steps, warmup, torch, H)
+        tm = H.ckks_th_traffic_model(prm.log_n, level, prm.alpha, split, 64, 64, paper_parallelism(level, K, split))
+        rows.append({"split": list(split), "ms": ms / steps,
+                     "library_ms": H.ckks_lt_predict(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, split, 64) * 1e3,
+                     "paper_bytes": tm["total_bytes"]})
+        torch.cuda.empty_cache()
+    t = [r["ms"] for r in rows]
+    b = [r["paper_bytes"] for r in rows]
+    ms_per_byte = sum(x * y for x, y in zip(b, t)) / sum(x * x for x in b)
+    for r in rows:
+        r["paper_ms"] = r["paper_bytes"] * ms_per_byte
+
+    def score(key):
+        err = [abs(r[key] - r["ms"]) / r["ms"] for r in rows]
+        pick = min(rows, key=lambda r: r[key])
+        best = min(t)
+        return {"mean_abs_err": round(sum(err) / len(err), 4), "max_abs_err": round(max(err), 4),
+                "spearman_vs_measured": round(_spearman([r[key] for r in rows], t), 3),
+                "pick": pick["split"], "pick_ms": round(pick["ms"], 4),
+                "pick_over_best": round(pick["ms"] / best, 4)}
+
+    best = min(rows, key=lambda r: r["ms"])
+    return {"level": level, "n_diag": 64, "steps": steps, "warmup": warmup,
+            "measured_best": best["split"], "measured_best_ms": round(best["ms"], 4),
+            "library_model": score("library_ms"),
+            "paper_table3_model": dict(score("paper_ms"), fitted_GB_per_s=round(1e-6 / ms_per_byte, 1)),
+            "splits": [{"split": r["split"], "ms": round(r["ms"], 4), "library_ms": round(r["library_ms"], 4),
+                        "paper_bytes": r["paper_bytes"], "paper_ms": round(r["paper_ms"], 4)} for r in rows],
+            "note": "library model: 4 rates fitted on MI355X; paper model: Table III's bytes over one fitted bandwidth"}
+
+
 def chain_leg(P, prm, steps, torch, H):
     """Factored DFT-like chain: 4 sparse LTs (15 diagonals at j 16^s, the
     last stage merged onto 8 offsets), one rescale each, level 24 -> 20."""
@@ -830,9 +901,7 @@ def main():
     # of a polynomial per kernel, up to 8 keys x 8 digit sets per key-switch
     # launch, the n3 accumulators of the multiply-accumulate in registers),
     # against the HBM bytes the counters measured per LT and the step time
-    n1s, n2s, n3s = th_split
-    par = dict(m1=1, l1=level + 1, m2=max(1, n1s - 1), l2=K, m3=min(8, max(1, n2s - 1)), m4=min(8, n1s), l3=K,
-               m5=min(8, n3s), l4=K, m6=max(1, n3s - 1), l5=K)
+    par = paper_parallelism(level, K, th_split)
     tm = H.ckks_th_traffic_model(prm.log_n, level, prm.alpha, th_split, 64, 64, par)
     measured = None
     if hbm:
@@ -904,6 +973,9 @@ def main():
         b = batched_leg(P, prm, args.batch_items, 3, torch, H)
         out["batched_ragged"] = b
         print("batched legs done", flush=True, file=sys.stderr)
+    if not args.no_sweep:
+        out["split_sweep"] = split_sweep_leg(P, prm, level, 10, 20, torch, H)
+        print("split sweep done", flush=True, file=sys.stderr)
     if not args.no_chain:
         out["dft_chain"] = chain_leg(P, prm, 10, torch, H)
         print("chain leg done", flush=True, file=sys.stderr)
