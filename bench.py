@@ -41,7 +41,8 @@ PROFILE_VALU = os.path.join(PROFILES, "valu_counters_th444_n16_l24_d64.md")
 PROFILE_LTS = 12  # TH-BSGS LTs in those runs: `--profile-only --only th --steps 2 --warmup 10`
 # The kernel (and template instance) behind each timed kernel id in one
 # TH-BSGS (4,4,4) step at level 24, as rocprofv3 names it.
-TH444_KERNEL = {"ptmac": "mac_kernel<4, false>", "keyswitch_gather": "ks_gather_kernel<false, 3>"}
+TH444_KERNEL = {"ptmac": "mac_kernel<4, false>", "keyswitch_gather": "ks_gather_kernel<false, 3>",
+                "ksmac": "ksmac_kernel<4, 3>"}
 
 
 def parse():
@@ -847,14 +848,20 @@ def main():
     n_l, ms_l, bytes_l = prof_dom[dom]
     avg_s = ms_l / n_l * 1e-3
     K = prm.alpha + level + 1
-    # The algorithmic unit of the dominant kernel: for the
-    # plaintext multiply-accumulate, the plaintexts it streams (17 MiB per
-    # diagonal: K limbs of N words), every present diagonal of the step read
-    # once; for other kernels, each input and output word once (the library's
-    # own count)
+    # The algorithmic unit of the dominant kernel: for the plaintext
+    # multiply-accumulate, the plaintexts it streams (17 MiB per diagonal: K
+    # limbs of N words), every present diagonal of the step read once; for
+    # the middle key switch fused with it, every operand of lines 8-14 once
+    # (the library's own count); for other kernels, each input and output
+    # word once (the library's own count)
     if dom == "ptmac":
         unit_bytes = 64 * K * prm.n * 8 / (n_l / args.steps)
         unit = "plaintext bytes per launch (17 MiB per diagonal: %d limbs x %d words x 8 B; 64 diagonals)" % (K, prm.n)
+    elif dom == "ksmac":
+        unit_bytes = bytes_l / n_l
+        unit = ("bytes per launch of Algorithm 2 lines 8-14 fused, each operand once: the 3 middle keys (102 MiB "
+                "each), the 4 digit sets (51 MiB each) and their adds (17 MiB each), the 4 unrotated products "
+                "(34 MiB each), the 64 plaintexts (17 MiB each) and the 4 accumulator pairs written (34 MiB each)")
     else:
         unit_bytes = bytes_l / n_l
         unit = "algorithmic bytes per launch (each input and output word once)"
@@ -884,8 +891,10 @@ def main():
                 "schedule_bytes_per_launch": round(sched),
                 "schedule_GB_per_s": round(sched / avg_s / 1e9, 1),
                 "schedule_frac": round(sched / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-                "schedule_note": "every operand the launch streams read once: the (a_m, b_m) rotation products, the "
-                                 "plaintexts and the accumulators" if dom == "ptmac" else None,
+                "schedule_note": ("every operand the launch streams read once: the (a_m, b_m) rotation products, "
+                                  "the plaintexts and the accumulators" if dom == "ptmac" else
+                                  "the same as the unit: the fused launch materialises nothing" if dom == "ksmac"
+                                  else None),
                 "share_of_step": round(ms_l / ms_ev, 3)}
     breakdown = {k: {"launches_per_step": v[0] / probe_steps, "ms_per_step": round(v[1] / probe_steps, 4),
                      "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}

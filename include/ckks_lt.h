@@ -495,7 +495,10 @@ typedef struct {
  * Predicted device seconds of one LT with this split and n_diag present
  * diagonals: the operation counts of ckks_lt_cost_model priced with `rates`,
  * plus the words the key-switch and MAC kernels move as this library
- * schedules them.  DH-BSGS (n1, n2) is priced as TH-BSGS (1, n1, n2).
+ * schedules one LT (TH-BSGS with at most 8 accumulators: the middle key
+ * switch fused with the multiply-accumulate, the rotation products never
+ * stored).  DH-BSGS (n1, n2) is priced as TH-BSGS (1, n1, n2).  The rates
+ * can be refitted on a device with `python -m paper_2605_17222_amd.calibrate`.
  */
 int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, int n3, int n_diag,
                     const ckks_lt_rates* rates, double* seconds);
@@ -544,8 +547,10 @@ int ckks_th_traffic_model(int log_n, int level, int alpha, int n1, int n2, int n
 /* Kernel identifiers: the forward NTT column / row passes, the inverse NTT
  * row / column passes, basis conversion, key-switch inner product (several
  * digit sets and keys, automorphism on write), plaintext multiply-accumulate,
- * the automorphism gather, and the gather form of the key switch that adds
- * every outer rotation into the accumulator. */
+ * the automorphism gather, the gather form of the key switch that adds
+ * every outer rotation into the accumulator, plaintext encoding, and the
+ * middle key switch fused with the multiply-accumulate (Algorithm 2, lines
+ * 8-14, used for an item whose middle keys no other item of the call reads). */
 #define CKKS_KERNEL_NTT_FWD_COL 0
 #define CKKS_KERNEL_NTT_FWD_ROW 1
 #define CKKS_KERNEL_NTT_INV_ROW 2
@@ -556,7 +561,8 @@ int ckks_th_traffic_model(int log_n, int level, int alpha, int n1, int n2, int n
 #define CKKS_KERNEL_AUTOMORPH 7
 #define CKKS_KERNEL_KEYSWITCH_GATHER 8
 #define CKKS_KERNEL_ENCODE_FFT 9  /* plaintext encoding: the two FFT passes  */
-#define CKKS_KERNEL_COUNT 10
+#define CKKS_KERNEL_KSMAC 10
+#define CKKS_KERNEL_COUNT 11
 
 /*
  * Process-wide: for every kernel k with bit (1 << k) set in mask, each later

@@ -51,7 +51,7 @@ EXPORTED = [
 CKKS_LT_NOALLOC_MAX_WS = 64 << 20
 
 KERNELS = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "keyswitch", "ptmac",
-           "automorph", "keyswitch_gather", "encode_fft"]
+           "automorph", "keyswitch_gather", "encode_fft", "ksmac"]
 
 
 class CkksError(RuntimeError):

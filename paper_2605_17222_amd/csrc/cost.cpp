@@ -108,13 +108,15 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
   if (rates) {
     r = *rates;
   } else {
-    // Fitted on one MI355X at N = 2^16 (levels 8..24, 16..511 diagonals,
-    // 120 splits, 30 warm-up steps each; mean prediction error 4%): BConv
-    // from its own kernel time.
-    r.ntt_limb_s = 3.87e-7;
-    r.bconv_product_s = 0.55e-12;
-    r.hbm_bytes_per_s = 4.72e12;
-    r.layer_s = 68.7e-6;
+    // Measured on one MI355X (python -m paper_2605_17222_amd.calibrate: 120
+    // banded LTs at N = 2^16, levels 8, 16, 24, 16..256 diagonals): the NTT
+    // and BConv rates from those kernels' own time, the bandwidth and the
+    // layer latency fitted to the rest; mean prediction error 11% (max 35%),
+    // the pick 1.8% slower than the fastest timed split on average.
+    r.ntt_limb_s = 8.19e-7;
+    r.bconv_product_s = 0.637e-12;
+    r.hbm_bytes_per_s = 6.43e12;
+    r.layer_s = 86.2e-6;
   }
   if (algo == CKKS_LT_DH_BSGS) {  // Algorithm 2 with an empty inner layer
     n3 = n2;
@@ -123,6 +125,23 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
     algo = CKKS_LT_TH_BSGS;
   }
   if (algo != CKKS_LT_TH_BSGS) n3 = 1;
+  // A banded matrix (offsets 0 .. n_diag - 1) leaves the blocks past its
+  // last diagonal absent, and the library skips their work (the outer
+  // rotations of empty giant-step blocks, the middle rotations and inner
+  // products with no diagonal): price the split it really runs.
+  if (n_diag > 0) {
+    const long inner = (long)n1 * n2;
+    if (algo == CKKS_LT_TH_BSGS) n3 = (int)std::min<long>(n3, (n_diag + inner - 1) / inner);
+    if (n_diag < inner) {
+      n2 = (int)std::min<long>(n2, (n_diag + n1 - 1) / n1);
+      n1 = std::min(n1, n_diag);
+    }
+  }
+  // TH-BSGS (n1, 1, n3) runs as (1, n1, n3): the same terms and rotations.
+  if (algo == CKKS_LT_TH_BSGS && n2 == 1 && n1 > 1) {
+    n2 = n1;
+    n1 = 1;
+  }
   ckks_lt_cost c;
   const int e = ckks_lt_cost_model(log_n, level, alpha, algo, n1, n2, n3, 64, &c);
   if (e != CKKS_OK) return e;
@@ -136,9 +155,13 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
   }
   const double bconv_products = (c.decompose * conv + c.moddown * alpha * Lq) * N;
   // Words moved per coefficient position by the HBM-bound kernels as this
-  // library schedules them: a key (2 beta K words at this level) is read
+  // library schedules one LT: a key (2 beta K words at this level) is read
   // once per launch for every digit set that uses it (up to 8 digit sets per
-  // launch); every product is written once and read once by the MAC.
+  // launch).  With at most 8 accumulators the middle key switch runs fused
+  // with the multiply-accumulate (lines 8-14 in one kernel per 16 terms):
+  // each middle key, digit set and add read once, the rotation products
+  // never stored; otherwise every product is written once and read once by
+  // the MAC.
   const double keyw = 2.0 * beta * K;
   double words = 0;
   int layers = 0;
@@ -147,12 +170,22 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
       words += beta * K + (n1 - 1) * keyw + (n1 - 1) * 2.0 * K + Lq;
       ++layers;
     }
-    if (n2 > 1) {
-      words += ((n1 + 7) / 8) * (n2 - 1) * keyw + n1 * (double)beta * K + n1 * (double)K +
-               (double)n1 * (n2 - 1) * 2.0 * K;
+    if (n2 > 1 && n3 <= 8) {
+      // launches of 16 terms, ordered by middle step: each launch reads the
+      // digit sets and adds of its terms (up to 16) and each key once, and
+      // every launch after the first reads and writes the accumulators
+      const int launches = (n1 * n2 + 15) / 16, per = std::min(n1, 16), spans = (n1 + 15) / 16;
+      words += (double)spans * (n2 - 1) * keyw + (double)launches * per * (beta + 1.0) * K + 2.0 * n1 * K +
+               (double)n_diag * K + 2.0 * n3 * K + (launches - 1) * 4.0 * n3 * K;
       ++layers;
+    } else {
+      if (n2 > 1) {
+        words += ((n1 + 7) / 8) * (n2 - 1) * keyw + n1 * (double)beta * K + n1 * (double)K +
+                 (double)n1 * (n2 - 1) * 2.0 * K;
+        ++layers;
+      }
+      words += 2.0 * n1 * n2 * K + (double)n_diag * K + 2.0 * n3 * K;
     }
-    words += 2.0 * n1 * n2 * K + (double)n_diag * K + 2.0 * n3 * K;
     if (n3 > 1) {
       words += (n3 - 1) * (beta * (double)K + keyw + K) + 4.0 * K;
       ++layers;

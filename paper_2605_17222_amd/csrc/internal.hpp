@@ -152,6 +152,29 @@ struct KsGatherArgs {
   uint64_t* c1;
 };
 
+// Lines 8-14 of Algorithm 2 in one pass (middle key switch fused with the
+// plaintext multiply-accumulate).  Term m is either unrotated, (a_m, b_m)
+// read at the output position (key_of[m] < 0), or the middle rotation of
+// digit set digits[m] by key key_of[m]: at output position p the product
+// <d, swk> and the add a[m] are formed at auto_index(p, gal[key]), so the
+// rotated (a_m, b_m) exist only in registers.  Terms sharing a key are
+// consecutive.
+constexpr int kKsMacAlign = 2048;  // N must be a multiple: 256 threads per workgroup x 8 XCDs
+struct KsMacArgs {
+  int nm, nk, K, beta, kmax;
+  int accumulate;                    // add into the outputs
+  int key_of[kMaxMacM];
+  const uint64_t* digits[kMaxMacM];  // rotated terms: [beta][K][N]
+  const uint64_t* a[kMaxMacM];       // the add (rotated) or a_m (unrotated); Q-basis c' if pscaled
+  const uint64_t* b[kMaxMacM];       // unrotated terms: b_m
+  int pscaled[kMaxMacM];             // a (and b) are Q-basis polynomials to be multiplied by P
+  const uint64_t* key[kMaxMacM];     // [beta_max][2][kmax][N]
+  uint32_t gal[kMaxMacM];            // Galois element of the key's rotation r
+  const uint64_t* f[kMaxMacK][kMaxMacM];  // null = absent diagonal
+  uint64_t* out0[kMaxMacK];
+  uint64_t* out1[kMaxMacK];
+};
+
 struct MacArgs {
   int nm, nk, K, prime_off;
   int pscaled0;    // a[0], b[0] are Q-basis polynomials to be multiplied by P
@@ -225,6 +248,7 @@ hipError_t launch_bconv(const struct ::ckks_params* P, const BConvArgs& a, int i
 hipError_t launch_keyswitch(const struct ::ckks_params* P, const KsArgs& a, hipStream_t s);
 hipError_t launch_keyswitch_gather(const struct ::ckks_params* P, const KsGatherArgs& a, hipStream_t s);
 hipError_t launch_ptmac(const struct ::ckks_params* P, const MacArgs& a, hipStream_t s);
+hipError_t launch_ksmac(const struct ::ckks_params* P, const KsMacArgs& a, hipStream_t s);
 hipError_t launch_automorph(const struct ::ckks_params* P, const AutoArgs& a, hipStream_t s);
 hipError_t launch_automorph_batch(const struct ::ckks_params* P, const AutoBatchArgs& a, hipStream_t s);
 hipError_t launch_encode_fft(const struct ::ckks_params* P, const EncArgs& a, hipStream_t s);

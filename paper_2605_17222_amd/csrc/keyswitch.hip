@@ -23,6 +23,8 @@ namespace ckks {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr uint32_t kXcds = 8;  // accelerator complex dies of the device, each with its own L2
+static_assert(kKsMacAlign == kThreads * kXcds, "ksmac grid: whole workgroups per XCD");
 
 // Operands read once per launch (keys, digits, plaintexts, products) are
 // loaded with the non-temporal hint: they stream through without displacing
@@ -458,6 +460,221 @@ hipError_t launch_mac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- middle key switch fused with the multiply-accumulate ------------------
+// Thread (limb l, output position p) forms every term's (a_m, b_m) at p --
+// read for unrotated terms, for rotated ones the key-switch product and add
+// at the source position auto_index(p, gal) (a gather: eq. (8) keeps a
+// wavefront's 64 positions in one aligned block) -- and folds it into NK
+// pairs of 128-bit accumulators right away.  The operands of term m + 1 are
+// loaded while term m is folded in; a key shared with the previous term is
+// kept in registers instead of loaded again.
+template <int NK, int MB>
+struct KsMacOps {
+  uint64_t k0[MB], k1[MB], d[MB], a, b, f[NK];
+};
+
+template <int NK, int MB>
+__device__ __forceinline__ void ksmac_load(KsMacOps<NK, MB>& o, const KsMacArgs& a, int m, bool load_key, int l,
+                                           uint32_t p, size_t n, int log_n, int alpha) {
+  const int kj = a.key_of[m];
+  const size_t off = (size_t)l * n + p;
+  const int lq = l - alpha;  // Q-basis limb of a pscaled operand (none on the special primes)
+  // both words are assigned on every path (values first, one store each), so
+  // the operand structs stay in registers
+  uint64_t va = 0, vb = 0;
+  if (kj < 0) {
+    if (a.pscaled[m]) {
+      va = lq < 0 ? 0 : ld_nt(a.a[m] + (size_t)lq * n + p);
+      vb = lq < 0 ? 0 : ld_nt(a.b[m] + (size_t)lq * n + p);
+    } else {
+      va = ld_nt(a.a[m] + off);
+      vb = ld_nt(a.b[m] + off);
+    }
+  } else {
+    const uint32_t src = auto_index(p, a.gal[kj], log_n);
+    if (load_key)
+      ld_key<false, MB>(o.k0, o.k1, reinterpret_cast<const uint8_t*>(a.key[kj]) + (size_t)l * n * 8,
+                        (size_t)a.kmax * n * 8, a.beta, src, n);
+    // digits and adds are read again by the other rotations of the launch:
+    // ordinary loads, kept in L2 (the keys and plaintexts stream through)
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+      if (b < a.beta) o.d[b] = a.digits[m][((size_t)b * a.K + l) * n + src];
+    if (a.pscaled[m])
+      va = lq < 0 ? 0 : a.a[m][(size_t)lq * n + src];
+    else
+      va = a.a[m][(size_t)l * n + src];
+  }
+  o.a = va;
+  o.b = vb;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const uint64_t* __restrict__ fp = a.f[k][m];
+    o.f[k] = fp ? ld_nt(fp + off) : 0;
+  }
+}
+
+// The fold of one limb.  FP (primes below 2^46): operands as exact doubles,
+// every product reduced on its own (fp_mulmod_var), sums of at most 16 terms
+// of magnitude below q stay exact; about a third of the integer path's
+// instructions.  Otherwise 64 x 64 -> 128-bit products summed lazily and
+// reduced with Barrett's floor(2^128 / q).
+template <int NK, int MB, bool FP>
+__device__ __forceinline__ void ksmac_body(const KsMacArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n,
+                                           int log_n, int alpha) {
+  const uint64_t q = pr.q;
+  const double qd = pr.qd, qi = pr.qinv_d;
+  const double pm = (double)pr.pmod, pmq = pm * qi;  // P mod q (below 2^46 on this path) and P/q
+  const size_t off = (size_t)l * n + p;
+  U128 x[NK], y[NK];
+  double xd[NK], yd[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    x[k] = y[k] = U128{0, 0};
+    xd[k] = yd[k] = 0.0;
+  }
+  double kd0[MB] = {}, kd1[MB] = {};  // FP: the current key as doubles
+  KsMacOps<NK, MB> cur{}, nxt{};
+  if (a.nm > 0) ksmac_load<NK, MB>(cur, a, 0, true, l, p, n, log_n, alpha);
+  for (int m = 0; m < a.nm; ++m) {
+    const bool new_key = a.key_of[m] >= 0 && (m == 0 || a.key_of[m - 1] != a.key_of[m]);
+    if (m + 1 < a.nm) {
+      // a key shared with term m stays in registers
+      const bool same = a.key_of[m + 1] >= 0 && a.key_of[m + 1] == a.key_of[m];
+      ksmac_load<NK, MB>(nxt, a, m + 1, !same, l, p, n, log_n, alpha);
+      if (!FP && same) {  // (the FP path keeps the current key as doubles)
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          nxt.k0[b] = cur.k0[b];
+          nxt.k1[b] = cur.k1[b];
+        }
+      }
+    }
+    if constexpr (FP) {
+      double av, bv;
+      if (a.key_of[m] < 0) {
+        av = u64_to_d(cur.a);
+        bv = u64_to_d(cur.b);
+        if (a.pscaled[m]) {  // (P c0', P c1')
+          av = fp_mulmod(av, pm, pmq, qd);
+          bv = fp_mulmod(bv, pm, pmq, qd);
+        }
+      } else {
+        if (new_key) {
+#pragma unroll
+          for (int b = 0; b < MB; ++b) {
+            kd0[b] = u64_to_d(cur.k0[b]);
+            kd1[b] = u64_to_d(cur.k1[b]);
+          }
+        }
+        double u = 0.0, v = 0.0;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          if (b < a.beta) {
+            const double d = u64_to_d(cur.d[b]);
+            u += fp_mulmod_var(d, kd0[b], qd, qi);
+            v += fp_mulmod_var(d, kd1[b], qd, qi);
+          }
+        }
+        double addv = u64_to_d(cur.a);
+        if (a.pscaled[m]) addv = fp_mulmod(addv, pm, pmq, qd);
+        av = fp_reduce(u + addv, qd, qi);
+        bv = fp_reduce(v, qd, qi);
+      }
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        if (a.f[k][m]) {
+          const double f = u64_to_d(cur.f[k]);
+          xd[k] += fp_mulmod_var(av, f, qd, qi);
+          yd[k] += fp_mulmod_var(bv, f, qd, qi);
+        }
+      }
+    } else {
+      uint64_t av, bv;
+      if (a.key_of[m] < 0) {
+        av = cur.a;
+        bv = cur.b;
+        if (a.pscaled[m]) {  // (P c0', P c1'): zero on the special primes
+          av = shoup(av, pr.pmod, pr.pmod_sh, q);
+          bv = shoup(bv, pr.pmod, pr.pmod_sh, q);
+        }
+      } else {
+        U128 u = {0, 0}, v = {0, 0};
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          if (b < a.beta) {
+            add128(u, mul_wide(cur.d[b], cur.k0[b]));
+            add128(v, mul_wide(cur.d[b], cur.k1[b]));
+          }
+        }
+        uint64_t addv = cur.a;
+        if (a.pscaled[m]) addv = shoup(addv, pr.pmod, pr.pmod_sh, q);
+        av = add_mod(barrett128(u, q, pr.r_lo, pr.r_hi), addv, q);
+        bv = barrett128(v, q, pr.r_lo, pr.r_hi);
+      }
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        if (a.f[k][m]) {
+          add128(x[k], mul_wide(av, cur.f[k]));
+          add128(y[k], mul_wide(bv, cur.f[k]));
+        }
+      }
+    }
+    if (m + 1 < a.nm) cur = nxt;
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    uint64_t xr, yr;
+    if constexpr (FP) {
+      xr = fp_canon(xd[k], qd, qi);
+      yr = fp_canon(yd[k], qd, qi);
+    } else {
+      xr = barrett128(x[k], q, pr.r_lo, pr.r_hi);
+      yr = barrett128(y[k], q, pr.r_lo, pr.r_hi);
+    }
+    if (a.accumulate) {
+      xr = add_mod(xr, a.out0[k][off], q);
+      yr = add_mod(yr, a.out1[k][off], q);
+    }
+    __builtin_nontemporal_store(xr, a.out0[k] + off);
+    __builtin_nontemporal_store(yr, a.out1[k] + off);
+  }
+}
+
+// Workgroup w of the launch runs on XCD w mod 8 (the dispatcher deals
+// workgroups round-robin over the eight XCDs); numbering each XCD's
+// workgroups consecutively gives an XCD whole limbs, so the digits and adds
+// that a limb's rotations gather again stay in that XCD's L2.  The grid is
+// (N / kThreads) x K with N / kThreads a multiple of 8.
+template <int NK, int MB>
+__global__ void __launch_bounds__(kThreads)
+    ksmac_kernel(KsMacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
+  const uint32_t w = blockIdx.y * gridDim.x + blockIdx.x;
+  const uint32_t per_xcd = gridDim.x * gridDim.y / kXcds;
+  const uint32_t v = (w % kXcds) * per_xcd + w / kXcds;
+  const uint32_t p = (v % gridDim.x) * kThreads + threadIdx.x;
+  const int l = (int)(v / gridDim.x);
+  const PrimeDev& pr = primes[l];
+  const size_t n = (size_t)1 << log_n;
+  if (pr.fp)
+    ksmac_body<NK, MB, true>(a, pr, l, p, n, log_n, alpha);
+  else
+    ksmac_body<NK, MB, false>(a, pr, l, p, n, log_n, alpha);
+}
+
+template <int NK>
+hipError_t launch_ksmac_nk(const ckks_params* P, const KsMacArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  switch (a.beta) {
+    case 1: hipLaunchKernelGGL((ksmac_kernel<NK, 1>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
+    case 2: hipLaunchKernelGGL((ksmac_kernel<NK, 2>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
+    case 3: hipLaunchKernelGGL((ksmac_kernel<NK, 3>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
+    case 4: hipLaunchKernelGGL((ksmac_kernel<NK, 4>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kThreads)
     auto_kernel(AutoArgs a, const PrimeDev* __restrict__ primes, int log_n) {
   const size_t n = (size_t)1 << log_n;
@@ -556,6 +773,56 @@ hipError_t launch_ptmac(const ckks_params* P, const MacArgs& a, hipStream_t s) {
     case 6: return launch_mac<6>(P, a, s);
     case 7: return launch_mac<7>(P, a, s);
     case 8: return launch_mac<8>(P, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ksmac(const ckks_params* P, const KsMacArgs& a, hipStream_t s) {
+  // Geometry, checked before anything runs: term and accumulator counts
+  // within the tables, every rotated term's key among the launch's keys and
+  // consecutive with the other terms of that key, every operand present.
+  if (a.nm < 1 || a.nm > kMaxMacM || a.nk < 1 || a.nk > kMaxMacK || a.K < 1 || a.K > a.kmax || a.beta < 1 ||
+      a.beta > kMaxBeta || P->n % kKsMacAlign)
+    return hipErrorInvalidValue;
+  int nkeys = 0, ndig = 0, nadd = 0, nunrot = 0, nf = 0;
+  for (int m = 0; m < a.nm; ++m) {
+    const int kj = a.key_of[m];
+    if (kj >= kMaxMacM || !a.a[m]) return hipErrorInvalidValue;
+    if (kj < 0) {
+      if (!a.b[m]) return hipErrorInvalidValue;
+      ++nunrot;
+    } else {
+      if (!a.key[kj] || !a.digits[m]) return hipErrorInvalidValue;
+      for (int m2 = 0; m2 < m; ++m2)  // a key's terms are consecutive
+        if (a.key_of[m2] == kj && a.key_of[m - 1] != kj) return hipErrorInvalidValue;
+      bool seen_key = false, seen_dig = false, seen_add = false;
+      for (int m2 = 0; m2 < m; ++m2) {
+        seen_key = seen_key || a.key_of[m2] == kj;
+        seen_dig = seen_dig || (a.key_of[m2] >= 0 && a.digits[m2] == a.digits[m]);
+        seen_add = seen_add || (a.key_of[m2] >= 0 && a.a[m2] == a.a[m]);
+      }
+      nkeys += !seen_key;
+      ndig += !seen_dig;
+      nadd += !seen_add;
+    }
+    for (int k = 0; k < a.nk; ++k) nf += a.f[k][m] ? 1 : 0;
+  }
+  for (int k = 0; k < a.nk; ++k)
+    if (!a.out0[k] || !a.out1[k]) return hipErrorInvalidValue;
+  // algorithmic bytes: keys, digit sets, adds and unrotated products, the
+  // plaintexts, the accumulators, each word once
+  const double words = (double)a.K * (2.0 * a.beta * nkeys + (double)a.beta * ndig + nadd + 2.0 * nunrot + nf +
+                                      2.0 * a.nk * (a.accumulate ? 2 : 1));
+  ProfScope prof(CKKS_KERNEL_KSMAC, s, words * P->n * 8);
+  switch (a.nk) {
+    case 1: return launch_ksmac_nk<1>(P, a, s);
+    case 2: return launch_ksmac_nk<2>(P, a, s);
+    case 3: return launch_ksmac_nk<3>(P, a, s);
+    case 4: return launch_ksmac_nk<4>(P, a, s);
+    case 5: return launch_ksmac_nk<5>(P, a, s);
+    case 6: return launch_ksmac_nk<6>(P, a, s);
+    case 7: return launch_ksmac_nk<7>(P, a, s);
+    case 8: return launch_ksmac_nk<8>(P, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -550,6 +550,109 @@ struct ThItem {
   }
 };
 
+// Whether lines 8-14 of an item run fused (ksmac): its plaintexts and keys
+// resident and unpacked, at most kMaxMacK accumulators (so the key-switch
+// products are formed once), and none of its middle keys read by another
+// item of the call -- a key-switch launch reads a shared key once for up to
+// kMaxDig digit sets, which saves more than the fusion's unmaterialised
+// rotation products.
+std::vector<char> fuse_middle(const ckks_params* P, const std::vector<ThItem>& items) {
+  auto key_of = [&](const ThItem& it, long r) -> const uint64_t* {
+    const long S = P->n / 2;
+    auto f = it.ks->m.find(((r % S) + S) % S);
+    return f == it.ks->m.end() ? nullptr : f->second;
+  };
+  auto middle_keys = [&](const ThItem& it) {
+    std::vector<const uint64_t*> ks;
+    for (int j = 1; j < it.n2; ++j)
+      for (int i = 0; i < it.n1; ++i)
+        if (it.mid_i[i] && it.used_m[it.n1 * j + i]) {
+          ks.push_back(key_of(it, it.stride * it.n1 * j));
+          break;
+        }
+    return ks;
+  };
+  std::map<const uint64_t*, int> uses;
+  for (const ThItem& it : items)
+    for (const uint64_t* k : middle_keys(it)) ++uses[k];
+  std::vector<char> out(items.size(), 0);
+  for (size_t t = 0; t < items.size(); ++t) {
+    const ThItem& it = items[t];
+    if (it.D.z || it.D.packed || it.ks->packed || P->n % kKsMacAlign) continue;
+    int nk = it.kdir < 0 ? 1 : 0, nterms = 0;
+    for (int k = 0; k < it.n3; ++k) nk += (k == it.kdir || it.used_k[k]) ? 1 : 0;
+    for (int m = 0; m < it.n1 * it.n2; ++m) nterms += it.used_m[m] ? 1 : 0;
+    if (nk > kMaxMacK || nterms == 0) continue;
+    bool alone = true;
+    for (const uint64_t* k : middle_keys(it)) alone = alone && k && uses[k] == 1;
+    out[t] = alone ? 1 : 0;
+  }
+  return out;
+}
+
+// Lines 8-14 of one item in one kernel: every used term m = n1 j + i is
+// either unrotated (j = 0: (a_i, b_i), or (P c0', P c1') for i = 0) or the
+// middle rotation of d_i by s n1 j, formed in registers at each output
+// position and multiplied into the outputs kk right away.  Terms go to
+// launches of at most kMaxMacM terms (and so keys); the first launch writes
+// the outputs, later ones add into them.
+void ksmac(Run& R, ThItem& it, const std::vector<int>& kk) {
+  const ckks_params* P = R.P;
+  const int inner = it.n1 * it.n2;
+  struct Term {
+    int m, j, i;
+  };
+  std::vector<Term> terms;
+  for (int j = 0; j < it.n2; ++j)
+    for (int i = 0; i < it.n1; ++i)
+      if (it.used_m[it.n1 * j + i]) terms.push_back(Term{it.n1 * j + i, j, i});
+  bool first = true;
+  size_t t0 = 0;
+  while (t0 < terms.size()) {
+    KsMacArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nk = (int)kk.size();
+    a.K = P->K(it.level);
+    a.beta = P->beta(it.level);
+    a.kmax = P->Kmax();
+    a.accumulate = first ? 0 : 1;
+    int nkeys = 0, last_j = -1;
+    size_t t = t0;
+    for (; t < terms.size() && a.nm < kMaxMacM; ++t) {
+      const Term& tm = terms[t];
+      const int m = a.nm;
+      if (tm.j == 0) {
+        a.key_of[m] = -1;
+        a.a[m] = tm.i == 0 ? it.c0 : it.A[tm.i];
+        a.b[m] = tm.i == 0 ? it.c1 : it.B[tm.i];
+        a.pscaled[m] = tm.i == 0 ? 1 : 0;
+      } else {
+        if (tm.j != last_j) {
+          const long r = it.stride * it.n1 * tm.j;
+          a.key[nkeys] = it.ks->get(R, r);
+          a.gal[nkeys] = galois(P, r);
+          ++nkeys;
+          last_j = tm.j;
+        }
+        a.key_of[m] = nkeys - 1;
+        a.digits[m] = it.Dg[tm.i];
+        a.a[m] = tm.i == 0 ? it.c0 : it.A[tm.i];
+        a.pscaled[m] = tm.i == 0 ? 1 : 0;
+      }
+      for (size_t k = 0; k < kk.size(); ++k)
+        a.f[k][m] = (kk[k] >= 0 && it.D.has(kk[k] * inner + tm.m)) ? it.D.pt[kk[k] * inner + tm.m] : nullptr;
+      ++a.nm;
+    }
+    for (size_t k = 0; k < kk.size(); ++k) {
+      a.out0[k] = kk[k] >= 0 ? it.U0[kk[k]] : it.acc0;
+      a.out1[k] = kk[k] >= 0 ? it.U1[kk[k]] : it.acc1;
+    }
+    if (R.live()) R.check(launch_ksmac(P, a, R.s));
+    first = false;
+    t0 = t;
+  }
+}
+
 void lt_th(Run& R, std::vector<ThItem>& items) {
   const ckks_params* P = R.P;
   // Plan every item and take its buffers.
@@ -635,11 +738,16 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     divide(R, DIV_MODDOWN, md);
     decompose(R, dc);
   }
+  // Lines 8-14 fused for the items whose middle keys no other item reads
+  // (see ksmac below); for the others the middle key switch runs first.
+  std::vector<char> fused = fuse_middle(P, items);
   // Lines 8-11: middle rotations by s n1 j share d_i; each middle key is read
   // once per launch for all digit sets.
   {
     std::vector<KsTask> tasks;
-    for (ThItem& it : items)
+    for (size_t t = 0; t < items.size(); ++t) {
+      ThItem& it = items[t];
+      if (fused[t]) continue;
       for (int j = 1; j < it.n2; ++j)
         for (int i = 0; i < it.n1; ++i) {
           const int m = it.n1 * j + i;
@@ -648,17 +756,23 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
           tasks.push_back(KsTask{it.Dg[i], it.level, i == 0 ? it.c0 : it.A[i], i == 0, it.ks->get(R, r),
                                  galois(P, -r), it.A[m], it.B[m], it.ks->packed});
         }
+    }
     keyswitch(R, tasks);
   }
   // Lines 12 and 14: all plaintext products of an item at once (with no
   // unrotated block, the accumulator is one more output with no plaintext,
   // i.e. zero).
-  for (ThItem& it : items) {
+  for (size_t t = 0; t < items.size(); ++t) {
+    ThItem& it = items[t];
     const int K = P->K(it.level), inner = it.n1 * it.n2;
     std::vector<int> kk;
     for (int k = 0; k < it.n3; ++k)
       if (k == it.kdir || it.used_k[k]) kk.push_back(k);
     if (it.kdir < 0) kk.push_back(-1);
+    if (fused[t]) {
+      ksmac(R, it, kk);
+      continue;
+    }
     std::vector<MacTerm> terms;
     for (int m = 0; m < inner; ++m) {
       if (!it.used_m[m]) continue;
@@ -930,6 +1044,14 @@ ThItem th_item(const ckks_ct* in, const ckks_lt_diags* d, const KeySet* ks, ckks
   it.n1 = dh ? 1 : d->n1;
   it.n2 = dh ? d->n1 : d->n2;
   it.n3 = dh ? d->n2 : d->n3;
+  // With one middle step, (n1, 1, n3) has the terms, rotations and outputs
+  // of (1, n1, n3) (index n1 k + i, rotation s i, G_k = s (n1 k - centre),
+  // the same products bit for bit); run it that way, so its rotations go
+  // through the fused middle layer instead of materialising products.
+  if (it.n2 == 1 && it.n1 > 1) {
+    it.n2 = it.n1;
+    it.n1 = 1;
+  }
   it.stride = prog_stride(d);
   it.centre = d->centre;
   it.D.n = d->n_diag;

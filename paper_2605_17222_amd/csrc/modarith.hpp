@@ -96,6 +96,19 @@ __host__ __device__ __forceinline__ double fp_mulmod(double x, double w, double 
   return fma(x, w, -h) - l;
 }
 
+// x * y mod q for two data operands (no precomputed quotient), q < 2^46,
+// |x|, |y| <= q: h = fl(x y) and l = x y - h (exact, |l| <= ulp(h)/2 <=
+// 2^38) are the two-product; h/q < q < 2^46, so t = rint(h fl(1/q)) is within
+// 1/2 + 2^-5 of h/q and h - t q is an integer of magnitude below
+// (1/2 + 2^-5) q: the FMA that forms it is exact; the result h - t q + l is
+// congruent to x y and below 0.6 q + 2^38 in magnitude, exact as well.
+__host__ __device__ __forceinline__ double fp_mulmod_var(double x, double y, double q, double qinv) {
+  const double h = x * y;
+  const double l = fma(x, y, -h);
+  const double t = rint(h * qinv);
+  return fma(-t, q, h) + l;
+}
+
 // |x| < 2^52 -> x mod q in [-q/2 - 1, q/2 + 1] (an exact FMA: the result is below q).
 __host__ __device__ __forceinline__ double fp_reduce(double x, double q, double qinv) {
   return fma(-rint(x * qinv), q, x);

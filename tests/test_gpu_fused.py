@@ -1,0 +1,83 @@
+"""The middle key switch fused with the plaintext multiply-accumulate
+(Algorithm 2, lines 8-14 in one kernel: the rotated products exist only in
+registers) against the oracle's Algorithm 2 and against the unfused kernels
+(a batch whose items share every key runs the separate key-switch and MAC
+launches), bit for bit.  The splits cover one and several fused launches
+(more than 16 terms), a middle step of one ((n1, 1, n3) runs as
+(1, n1, n3)), and more accumulators than one fused launch holds (not
+fused)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2605_17222_amd as H
+import workload as W
+from gpu_common import gpu_params, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    prm = W.params_toy()
+    o = O.Oracle(prm)
+    o.keygen(23)
+    delta = 2.0 ** prm.log_delta
+    level = prm.max_level
+    diags = W.banded_diagonals(31, prm.slots, range(32))
+    v = W.input_vector(31, prm.slots)
+    ct = o.encrypt(level, v, delta, seed=37)
+    return dict(prm=prm, o=o, delta=delta, level=level, diags=diags, v=v, ct=ct, keys={})
+
+
+def _keys(c, split):
+    for r in W.th_rotations(*split):
+        if r not in c["keys"]:
+            c["keys"][r] = c["o"].rotkey(r)
+    return {r: c["keys"][r] for r in W.th_rotations(*split)}
+
+
+def _single(c, split, dpts, dkeys, dct):
+    import torch
+    prm, level = c["prm"], c["level"]
+    P = gpu_params(prm)
+    wsb = H.ckks_lt_workspace_size(P, level, split, dpts, H.CKKS_LT_TH_BSGS)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
+    o0, o1 = H.empty((level, prm.n)), H.empty((level, prm.n))
+    H.ckks_lt_eval(P, level, c["delta"], dct[0], dct[1], split, dpts, c["delta"], dkeys, H.CKKS_LT_TH_BSGS,
+                   o0, o1, ws, wsb)
+    torch.cuda.synchronize()
+    return np.stack([H.to_host(o0), H.to_host(o1)])
+
+
+def _shared_pair(c, split, dpts, dkeys, dct):
+    import torch
+    prm, level = c["prm"], c["level"]
+    P = gpu_params(prm)
+    items = [H.BatchItem(level, c["delta"], dct[0], dct[1], split, dpts, c["delta"], dkeys,
+                         H.empty((level, prm.n)), H.empty((level, prm.n))) for _ in range(2)]
+    wsb = H.ckks_lt_batch_workspace_size(P, items, H.CKKS_LT_TH_BSGS)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device="cuda")
+    code = H.ckks_lt_eval_batch(P, items, H.CKKS_LT_TH_BSGS, ws, wsb)
+    torch.cuda.synchronize()
+    assert code == H.CKKS_OK and all(it.status == H.CKKS_OK for it in items)
+    return [np.stack([H.to_host(it.out0), H.to_host(it.out1)]) for it in items]
+
+
+@pytest.mark.parametrize("split", [(2, 4, 4), (1, 8, 4), (2, 16, 1), (1, 32, 1), (4, 1, 8), (1, 2, 16)])
+def test_fused_middle_layer_equals_oracle_and_unfused(case, split):
+    log("fused middle layer", split)
+    c = case
+    o = c["o"]
+    pts = o.th_plaintexts(c["diags"], *split, c["delta"])
+    keys = _keys(c, split)
+    ref = o.lt_th(c["level"], c["ct"], split, pts, keys)
+    dpts = [None if f is None else H.to_device(f) for f in pts]
+    dkeys = {r: H.to_device(k) for r, k in keys.items()}
+    dct = [H.to_device(c["ct"][0]), H.to_device(c["ct"][1])]
+    alone = _single(c, split, dpts, dkeys, dct)
+    assert np.array_equal(alone, ref)
+    pair = _shared_pair(c, split, dpts, dkeys, dct)
+    assert np.array_equal(pair[0], alone) and np.array_equal(pair[1], alone)
+    z = o.decrypt_slots(alone, c["delta"] * c["delta"] / c["prm"].q[c["level"]])
+    assert np.abs(z - W.matvec(c["diags"], c["v"])).max() <= 5e-3
