@@ -1,11 +1,11 @@
 """The middle key switch fused with the plaintext multiply-accumulate
 (Algorithm 2, lines 8-14 in one kernel: the rotated products exist only in
 registers) against the oracle's Algorithm 2 and against the unfused kernels
-(a batch whose items share every key runs the separate key-switch and MAC
-launches), bit for bit.  The splits cover one and several fused launches
-(more than 16 terms), a middle step of one ((n1, 1, n3) runs as
-(1, n1, n3)), and more accumulators than one fused launch holds (not
-fused)."""
+(packed keys run the separate key-switch and MAC launches), bit for bit,
+alone and as the items of a batch sharing every key.  The splits cover one
+and several fused launches (more than 16 terms), a middle step of one
+((n1, 1, n3) runs as (1, n1, n3)), and more accumulators than one fused
+launch holds (not fused)."""
 import numpy as np
 import pytest
 
@@ -77,6 +77,9 @@ def test_fused_middle_layer_equals_oracle_and_unfused(case, split):
     dct = [H.to_device(c["ct"][0]), H.to_device(c["ct"][1])]
     alone = _single(c, split, dpts, dkeys, dct)
     assert np.array_equal(alone, ref)
+    P = gpu_params(c["prm"])
+    unfused = _single(c, split, dpts, {r: H.ckks_pack(P, k) for r, k in dkeys.items()}, dct)
+    assert np.array_equal(unfused, alone)
     pair = _shared_pair(c, split, dpts, dkeys, dct)
     assert np.array_equal(pair[0], alone) and np.array_equal(pair[1], alone)
     z = o.decrypt_slots(alone, c["delta"] * c["delta"] / c["prm"].q[c["level"]])
