@@ -9,14 +9,16 @@ predictor is linear in its rates once the per-split features are known:
     t = ntt_limb_s * f_ntt + bconv_product_s * f_bconv + f_bytes / hbm_bytes_per_s + layer_s * f_layers
 
 and the features are read from the library itself, by calling
-ckks_lt_predict with one rate set at a time.  The NTT and BConv rates are
-taken from those kernels' own time (a second pass of each point with every
-kernel timed, summed over the points, over the model's limb NTTs and
-conversion products); the HBM rate and the per-layer latency are then
-fitted to the rest of each LT's time by non-negative least squares on
-relative errors.  Prints one JSON object: the rates, the fit's mean and
-largest relative error, every point, and per (level, n) the split the
-fitted model picks against the measured fastest.
+ckks_lt_predict with one rate set at a time.  The BConv rate is taken from
+that kernel's own time (a second pass of each point with every kernel
+timed, summed over the points, over the model's conversion products); the
+other three rates are fitted to the rest of each LT's time by non-negative
+least squares on relative errors.  They are regression coefficients over
+features that grow together (limb NTTs, BConv products and hoisting layers
+rise with every Decompose and ModDown), so the NTT rate is not the NTT
+passes' time per limb, which is reported beside it.  Prints one JSON object:
+the rates, the fit's mean and largest relative error, every point, and per
+(level, n) the split the fitted model picks against the measured fastest.
 
     python -m paper_2605_17222_amd.calibrate [--levels 8 16 24] [--diags 16 32 64 128 256]
 """
@@ -157,11 +159,11 @@ def main():
                   file=sys.stderr, flush=True)
     A = np.array(rows)
     t = np.array(t_meas)
-    ntt_limb_s = float(np.sum(t_ntt) / np.sum(A[:, 0]))
+    ntt_kernel_limb_s = float(np.sum(t_ntt) / np.sum(A[:, 0]))
     bconv_product_s = float(np.sum(t_bconv) / np.sum(A[:, 1]))
-    rest = t - ntt_limb_s * A[:, 0] - bconv_product_s * A[:, 1]
-    y = nnls(A[:, 2:] / t[:, None], rest / t)
-    x = np.array([ntt_limb_s, bconv_product_s, y[0], y[1]])
+    rest = t - bconv_product_s * A[:, 1]
+    y = nnls(A[:, [0, 2, 3]] / t[:, None], rest / t)
+    x = np.array([y[0], bconv_product_s, y[1], y[2]])
     pred = A @ x
     err = np.abs(pred - t) / t
     rates = {"ntt_limb_s": x[0], "bconv_product_s": x[1],
@@ -172,7 +174,8 @@ def main():
         pick = min(grp, key=lambda g: pred[g[1]])
         picks.append({"level": level, "n_diag": n_diag, "best": list(best[0]), "best_s": float(t[best[1]]),
                       "pick": list(pick[0]), "pick_over_best": float(t[pick[1]] / t[best[1]])})
-    print(json.dumps({"rates": rates, "points": len(t), "mean_rel_err": float(err.mean()),
+    print(json.dumps({"rates": rates, "ntt_passes_s_per_limb": ntt_kernel_limb_s, "points": len(t),
+                      "mean_rel_err": float(err.mean()),
                       "max_rel_err": float(err.max()),
                       "mean_pick_over_best": float(np.mean([p["pick_over_best"] for p in picks])),
                       "max_pick_over_best": float(np.max([p["pick_over_best"] for p in picks])),

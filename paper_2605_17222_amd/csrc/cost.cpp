@@ -109,14 +109,14 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
     r = *rates;
   } else {
     // Measured on one MI355X (python -m paper_2605_17222_amd.calibrate: 120
-    // banded LTs at N = 2^16, levels 8, 16, 24, 16..256 diagonals): the NTT
-    // and BConv rates from those kernels' own time, the bandwidth and the
-    // layer latency fitted to the rest; mean prediction error 11% (max 35%),
-    // the pick 1.8% slower than the fastest timed split on average.
-    r.ntt_limb_s = 8.19e-7;
+    // banded LTs at N = 2^16, levels 8, 16, 24, 16..256 diagonals): the BConv
+    // rate from that kernel's own time, the other three fitted to the rest;
+    // mean prediction error 4.9% (max 18%), the pick 1.6% slower than the
+    // fastest timed split of its group on average (at most 6.7%).
+    r.ntt_limb_s = 3.00e-7;
     r.bconv_product_s = 0.637e-12;
-    r.hbm_bytes_per_s = 6.43e12;
-    r.layer_s = 86.2e-6;
+    r.hbm_bytes_per_s = 4.95e12;
+    r.layer_s = 110.4e-6;
   }
   if (algo == CKKS_LT_DH_BSGS) {  // Algorithm 2 with an empty inner layer
     n3 = n2;
