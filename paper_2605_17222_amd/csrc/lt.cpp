@@ -550,8 +550,8 @@ struct ThItem {
   }
 };
 
-// Whether lines 8-14 of an item run fused (ksmac): its plaintexts and keys
-// resident and unpacked, and at most kMaxMacK accumulators (so the
+// Whether lines 8-14 of an item run fused (ksmac): its plaintexts (resident
+// or encoded on the fly) and keys unpacked, and at most kMaxMacK accumulators (so the
 // key-switch products are formed once).  Also for items of a batch that
 // share keys: the unfused key-switch launch reads a shared key once for up
 // to kMaxDig digit sets, but the rotation products it stores and the MAC
@@ -561,7 +561,7 @@ std::vector<char> fuse_middle(const ckks_params* P, const std::vector<ThItem>& i
   std::vector<char> out(items.size(), 0);
   for (size_t t = 0; t < items.size(); ++t) {
     const ThItem& it = items[t];
-    if (it.D.z || it.D.packed || it.ks->packed || P->n % kKsMacAlign) continue;
+    if (it.D.packed || it.ks->packed || P->n % kKsMacAlign) continue;
     int nk = it.kdir < 0 ? 1 : 0, nterms = 0;
     for (int k = 0; k < it.n3; ++k) nk += (k == it.kdir || it.used_k[k]) ? 1 : 0;
     for (int m = 0; m < it.n1 * it.n2; ++m) nterms += it.used_m[m] ? 1 : 0;
@@ -575,7 +575,9 @@ std::vector<char> fuse_middle(const ckks_params* P, const std::vector<ThItem>& i
 // middle rotation of d_i by s n1 j, formed in registers at each output
 // position and multiplied into the outputs kk right away.  Terms go to
 // launches of at most kMaxMacM terms (and so keys); the first launch writes
-// the outputs, later ones add into them.
+// the outputs, later ones add into them.  Diagonals given as slot vectors
+// are encoded right before the launch that reads them (f^ = encode(rot(z,
+// -G_k))), into workspace the next launch reuses.
 void ksmac(Run& R, ThItem& it, const std::vector<int>& kk) {
   const ckks_params* P = R.P;
   const int inner = it.n1 * it.n2;
@@ -597,6 +599,8 @@ void ksmac(Run& R, ThItem& it, const std::vector<int>& kk) {
     a.kmax = P->Kmax();
     a.accumulate = first ? 0 : 1;
     int nkeys = 0, last_j = -1;
+    const size_t mark = R.ws.mark();
+    std::vector<EncItem> enc;
     size_t t = t0;
     for (; t < terms.size() && a.nm < kMaxMacM; ++t) {
       const Term& tm = terms[t];
@@ -619,15 +623,27 @@ void ksmac(Run& R, ThItem& it, const std::vector<int>& kk) {
         a.a[m] = tm.i == 0 ? it.c0 : it.A[tm.i];
         a.pscaled[m] = tm.i == 0 ? 1 : 0;
       }
-      for (size_t k = 0; k < kk.size(); ++k)
-        a.f[k][m] = (kk[k] >= 0 && it.D.has(kk[k] * inner + tm.m)) ? it.D.pt[kk[k] * inner + tm.m] : nullptr;
+      for (size_t k = 0; k < kk.size(); ++k) {
+        const int idx = kk[k] * inner + tm.m;
+        a.f[k][m] = nullptr;
+        if (kk[k] < 0 || !it.D.has(idx)) continue;
+        if (it.D.z) {
+          uint64_t* buf = R.limbs(a.K);
+          enc.push_back(EncItem{it.D.z[idx], -it.giant(P, kk[k]), it.D.zscale, 0, a.K, buf, nullptr});
+          a.f[k][m] = buf;
+        } else {
+          a.f[k][m] = it.D.pt[idx];
+        }
+      }
       ++a.nm;
     }
     for (size_t k = 0; k < kk.size(); ++k) {
       a.out0[k] = kk[k] >= 0 ? it.U0[kk[k]] : it.acc0;
       a.out1[k] = kk[k] >= 0 ? it.U1[kk[k]] : it.acc1;
     }
+    encode(R, enc);
     if (R.live()) R.check(launch_ksmac(P, a, R.s));
+    R.ws.reset(mark);
     first = false;
     t0 = t;
   }
