@@ -57,10 +57,14 @@ __global__ void __launch_bounds__(kThreads)
   }
   __syncthreads();
 
+  // An item with fewer source limbs than the launch's NS (a digit group
+  // shorter than alpha) has zeros in the remaining places: every product
+  // with them vanishes.
+  const int nsi = plan->ns;
   uint64_t y[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j)
-    y[j] = shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], primes[plan->src[j]].q);
+    y[j] = j < nsi ? shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], primes[plan->src[j]].q) : 0;
   if (plan->split30) {
     // all primes below 2^60: the inner product from 30-bit column sums
     uint32_t y0[NS], y1[NS];
@@ -95,18 +99,20 @@ hipError_t launch_ns(const ckks_params* P, const BConvArgs& a, int items, hipStr
 
 }  // namespace
 
-// All items of one launch have the same number of source limbs `ns`.
+// Every item of one launch has at most `ns` source limbs (the kernel's
+// unrolled count; shorter items are padded with zeros).
 hipError_t launch_bconv(const ckks_params* P, const BConvArgs& a, int items, int ns, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   // Launch geometry, checked on the host before anything runs: every item's
-  // plan converts from exactly ns limbs into at most max_nd <= kMaxDst limbs
+  // plan converts from 1 .. ns limbs into at most max_nd <= kMaxDst limbs
   // (so each workgroup's chunk [m0, m1) lies inside the plan and the grid
   // covers every destination), its buffers are set and the position grid
   // covers N exactly.
   if (items > kMaxConv || a.max_nd < 1 || a.max_nd > kMaxDst || P->n % kThreads) return hipErrorInvalidValue;
   for (int i = 0; i < items; ++i) {
     const std::pair<int, int> d = P->plan_dims(a.plan[i]);
-    if (d.first != ns || d.second < 1 || d.second > a.max_nd || !a.src[i] || !a.dst[i]) return hipErrorInvalidValue;
+    if (d.first < 1 || d.first > ns || d.second < 1 || d.second > a.max_nd || !a.src[i] || !a.dst[i])
+      return hipErrorInvalidValue;
   }
   ProfScope prof(CKKS_KERNEL_BCONV, s, (double)a.limbs_moved * P->n * 8);
   switch (ns) {

@@ -108,7 +108,7 @@ struct NttArgs {
 // out = (aux - v) * S^-1 mod q.
 enum EpiMode { EPI_NONE = 0, EPI_SUBMUL = 1 };
 
-constexpr int kMaxConv = 8;
+constexpr int kMaxConv = 16;
 struct BConvArgs {
   const BConvPlan* plan[kMaxConv];
   const uint64_t* src[kMaxConv];  // source limb j at src + j N
