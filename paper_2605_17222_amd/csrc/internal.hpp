@@ -163,12 +163,14 @@ constexpr int kKsMacAlign = 2048;  // N must be a multiple: 256 threads per work
 struct KsMacArgs {
   int nm, nk, K, beta, kmax;
   int accumulate;                    // add into the outputs
+  int key_packed, f_packed;          // every key / every plaintext of the launch is packed (else none is)
+  uint64_t pk_poly_bytes;            // bytes of one packed PQ polynomial
   int key_of[kMaxMacM];
   const uint64_t* digits[kMaxMacM];  // rotated terms: [beta][K][N]
   const uint64_t* a[kMaxMacM];       // the add (rotated) or a_m (unrotated); Q-basis c' if pscaled
   const uint64_t* b[kMaxMacM];       // unrotated terms: b_m
   int pscaled[kMaxMacM];             // a (and b) are Q-basis polynomials to be multiplied by P
-  const uint64_t* key[kMaxMacM];     // [beta_max][2][kmax][N]
+  const uint64_t* key[kMaxMacM];     // [beta_max][2][kmax][N], or packed [beta_max][2] polynomials
   uint32_t gal[kMaxMacM];            // Galois element of the key's rotation r
   const uint64_t* f[kMaxMacK][kMaxMacM];  // null = absent diagonal
   uint64_t* out0[kMaxMacK];

@@ -473,9 +473,14 @@ struct KsMacOps {
   uint64_t k0[MB], k1[MB], d[MB], a, b, f[NK];
 };
 
-template <int NK, int MB>
+// Layouts: KN / FN, the keys' / plaintexts' limb l is packed narrow (32-bit
+// and 8-bit planes); ko, ks: byte offset of limb l within a key polynomial
+// and the bytes between the key's polynomials; fo: byte offset of limb l
+// within a plaintext.
+template <int NK, int MB, bool KN, bool FN>
 __device__ __forceinline__ void ksmac_load(KsMacOps<NK, MB>& o, const KsMacArgs& a, int m, bool load_key, int l,
-                                           uint32_t p, size_t n, int log_n, int alpha) {
+                                           uint32_t p, size_t n, int log_n, int alpha, size_t ko, size_t ks,
+                                           size_t fo) {
   const int kj = a.key_of[m];
   const size_t off = (size_t)l * n + p;
   const int lq = l - alpha;  // Q-basis limb of a pscaled operand (none on the special primes)
@@ -492,9 +497,7 @@ __device__ __forceinline__ void ksmac_load(KsMacOps<NK, MB>& o, const KsMacArgs&
     }
   } else {
     const uint32_t src = auto_index(p, a.gal[kj], log_n);
-    if (load_key)
-      ld_key<false, MB>(o.k0, o.k1, reinterpret_cast<const uint8_t*>(a.key[kj]) + (size_t)l * n * 8,
-                        (size_t)a.kmax * n * 8, a.beta, src, n);
+    if (load_key) ld_key<KN, MB>(o.k0, o.k1, reinterpret_cast<const uint8_t*>(a.key[kj]) + ko, ks, a.beta, src, n);
     // digits and adds are read again by the other rotations of the launch:
     // ordinary loads, kept in L2 (the keys and plaintexts stream through)
 #pragma unroll
@@ -510,7 +513,7 @@ __device__ __forceinline__ void ksmac_load(KsMacOps<NK, MB>& o, const KsMacArgs&
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const uint64_t* __restrict__ fp = a.f[k][m];
-    o.f[k] = fp ? ld_nt(fp + off) : 0;
+    o.f[k] = fp ? ld_word<FN>(reinterpret_cast<const uint8_t*>(fp) + fo, p, n) : 0;
   }
 }
 
@@ -519,9 +522,12 @@ __device__ __forceinline__ void ksmac_load(KsMacOps<NK, MB>& o, const KsMacArgs&
 // of magnitude below q stay exact; about a third of the integer path's
 // instructions.  Otherwise 64 x 64 -> 128-bit products summed lazily and
 // reduced with Barrett's floor(2^128 / q).
-template <int NK, int MB, bool FP>
+template <int NK, int MB, bool FP, bool PK, bool PF, bool NARROW>
 __device__ __forceinline__ void ksmac_body(const KsMacArgs& a, const PrimeDev& pr, int l, uint32_t p, size_t n,
                                            int log_n, int alpha) {
+  constexpr bool KN = PK && NARROW, FN = PF && NARROW;
+  const size_t ko = limb_off(l, n, PK, pr), ks = poly_stride(PK, a.pk_poly_bytes, a.kmax, n);
+  const size_t fo = limb_off(l, n, PF, pr);
   const uint64_t q = pr.q;
   const double qd = pr.qd, qi = pr.qinv_d;
   const double pm = (double)pr.pmod, pmq = pm * qi;  // P mod q (below 2^46 on this path) and P/q
@@ -535,13 +541,13 @@ __device__ __forceinline__ void ksmac_body(const KsMacArgs& a, const PrimeDev& p
   }
   double kd0[MB] = {}, kd1[MB] = {};  // FP: the current key as doubles
   KsMacOps<NK, MB> cur{}, nxt{};
-  if (a.nm > 0) ksmac_load<NK, MB>(cur, a, 0, true, l, p, n, log_n, alpha);
+  if (a.nm > 0) ksmac_load<NK, MB, KN, FN>(cur, a, 0, true, l, p, n, log_n, alpha, ko, ks, fo);
   for (int m = 0; m < a.nm; ++m) {
     const bool new_key = a.key_of[m] >= 0 && (m == 0 || a.key_of[m - 1] != a.key_of[m]);
     if (m + 1 < a.nm) {
       // a key shared with term m stays in registers
       const bool same = a.key_of[m + 1] >= 0 && a.key_of[m + 1] == a.key_of[m];
-      ksmac_load<NK, MB>(nxt, a, m + 1, !same, l, p, n, log_n, alpha);
+      ksmac_load<NK, MB, KN, FN>(nxt, a, m + 1, !same, l, p, n, log_n, alpha, ko, ks, fo);
       if (!FP && same) {  // (the FP path keeps the current key as doubles)
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
@@ -646,7 +652,9 @@ __device__ __forceinline__ void ksmac_body(const KsMacArgs& a, const PrimeDev& p
 // workgroups consecutively gives an XCD whole limbs, so the digits and adds
 // that a limb's rotations gather again stay in that XCD's L2.  The grid is
 // (N / kThreads) x K with N / kThreads a multiple of 8.
-template <int NK, int MB>
+// PK / PF: the keys / plaintexts of the launch are packed; a packed narrow
+// limb (prime below 2^40, so on the FP64 path) is read from its planes.
+template <int NK, int MB, bool PK, bool PF>
 __global__ void __launch_bounds__(kThreads)
     ksmac_kernel(KsMacArgs a, const PrimeDev* __restrict__ primes, int log_n, int alpha) {
   const uint32_t w = blockIdx.y * gridDim.x + blockIdx.x;
@@ -656,20 +664,43 @@ __global__ void __launch_bounds__(kThreads)
   const int l = (int)(v / gridDim.x);
   const PrimeDev& pr = primes[l];
   const size_t n = (size_t)1 << log_n;
-  if (pr.fp)
-    ksmac_body<NK, MB, true>(a, pr, l, p, n, log_n, alpha);
+  if (pr.fp) {
+    if constexpr (PK || PF) {
+      if (pr.narrow) {
+        ksmac_body<NK, MB, true, PK, PF, true>(a, pr, l, p, n, log_n, alpha);
+        return;
+      }
+    }
+    ksmac_body<NK, MB, true, PK, PF, false>(a, pr, l, p, n, log_n, alpha);
+  } else {
+    ksmac_body<NK, MB, false, PK, PF, false>(a, pr, l, p, n, log_n, alpha);
+  }
+}
+
+template <int NK, int MB>
+void launch_ksmac_mb(const ckks_params* P, const KsMacArgs& a, hipStream_t s) {
+  dim3 grid(P->n / kThreads, a.K);
+  if (a.key_packed && a.f_packed)
+    hipLaunchKernelGGL((ksmac_kernel<NK, MB, true, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n,
+                       P->alpha);
+  else if (a.key_packed)
+    hipLaunchKernelGGL((ksmac_kernel<NK, MB, true, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n,
+                       P->alpha);
+  else if (a.f_packed)
+    hipLaunchKernelGGL((ksmac_kernel<NK, MB, false, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n,
+                       P->alpha);
   else
-    ksmac_body<NK, MB, false>(a, pr, l, p, n, log_n, alpha);
+    hipLaunchKernelGGL((ksmac_kernel<NK, MB, false, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n,
+                       P->alpha);
 }
 
 template <int NK>
 hipError_t launch_ksmac_nk(const ckks_params* P, const KsMacArgs& a, hipStream_t s) {
-  dim3 grid(P->n / kThreads, a.K);
   switch (a.beta) {
-    case 1: hipLaunchKernelGGL((ksmac_kernel<NK, 1>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
-    case 2: hipLaunchKernelGGL((ksmac_kernel<NK, 2>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
-    case 3: hipLaunchKernelGGL((ksmac_kernel<NK, 3>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
-    case 4: hipLaunchKernelGGL((ksmac_kernel<NK, 4>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, P->alpha); break;
+    case 1: launch_ksmac_mb<NK, 1>(P, a, s); break;
+    case 2: launch_ksmac_mb<NK, 2>(P, a, s); break;
+    case 3: launch_ksmac_mb<NK, 3>(P, a, s); break;
+    case 4: launch_ksmac_mb<NK, 4>(P, a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -810,10 +841,11 @@ hipError_t launch_ksmac(const ckks_params* P, const KsMacArgs& a, hipStream_t s)
   for (int k = 0; k < a.nk; ++k)
     if (!a.out0[k] || !a.out1[k]) return hipErrorInvalidValue;
   // algorithmic bytes: keys, digit sets, adds and unrotated products, the
-  // plaintexts, the accumulators, each word once
-  const double words = (double)a.K * (2.0 * a.beta * nkeys + (double)a.beta * ndig + nadd + 2.0 * nunrot + nf +
-                                      2.0 * a.nk * (a.accumulate ? 2 : 1));
-  ProfScope prof(CKKS_KERNEL_KSMAC, s, words * P->n * 8);
+  // plaintexts, the accumulators, each word once (packed limbs at their size)
+  const double words = (double)a.K * ((double)a.beta * ndig + nadd + 2.0 * nunrot + 2.0 * a.nk * (a.accumulate ? 2 : 1));
+  const double bytes = words * P->n * 8 + 2.0 * a.beta * nkeys * limb_bytes(P, a.K, a.key_packed) +
+                       nf * limb_bytes(P, a.K, a.f_packed);
+  ProfScope prof(CKKS_KERNEL_KSMAC, s, bytes);
   switch (a.nk) {
     case 1: return launch_ksmac_nk<1>(P, a, s);
     case 2: return launch_ksmac_nk<2>(P, a, s);

@@ -554,9 +554,9 @@ struct ThItem {
   }
 };
 
-// Whether lines 8-14 of an item run fused (ksmac): its plaintexts (resident
-// or encoded on the fly) and keys unpacked, and at most kMaxMacK accumulators (so the
-// key-switch products are formed once).  Also for items of a batch that
+// Whether lines 8-14 of an item run fused (ksmac): at most kMaxMacK
+// accumulators, so the key-switch products are formed once; resident or
+// encoded, plain or packed operands alike.  Also for items of a batch that
 // share keys: the unfused key-switch launch reads a shared key once for up
 // to kMaxDig digit sets, but the rotation products it stores and the MAC
 // reads back cost more (measured: 32 same-shape LTs 738 -> 768 LT/s, the
@@ -565,7 +565,7 @@ std::vector<char> fuse_middle(const ckks_params* P, const std::vector<ThItem>& i
   std::vector<char> out(items.size(), 0);
   for (size_t t = 0; t < items.size(); ++t) {
     const ThItem& it = items[t];
-    if (it.D.packed || it.ks->packed || P->n % kKsMacAlign) continue;
+    if (P->n % kKsMacAlign) continue;
     int nk = it.kdir < 0 ? 1 : 0, nterms = 0;
     for (int k = 0; k < it.n3; ++k) nk += (k == it.kdir || it.used_k[k]) ? 1 : 0;
     for (int m = 0; m < it.n1 * it.n2; ++m) nterms += it.used_m[m] ? 1 : 0;
@@ -602,6 +602,9 @@ void ksmac(Run& R, ThItem& it, const std::vector<int>& kk) {
     a.beta = P->beta(it.level);
     a.kmax = P->Kmax();
     a.accumulate = first ? 0 : 1;
+    a.key_packed = it.ks->packed ? 1 : 0;
+    a.f_packed = it.D.packed && !it.D.z ? 1 : 0;  // encoded plaintexts are written unpacked
+    a.pk_poly_bytes = P->pk_poly_bytes;
     int nkeys = 0, last_j = -1;
     const size_t mark = R.ws.mark();
     std::vector<EncItem> enc;

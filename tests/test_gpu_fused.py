@@ -1,7 +1,8 @@
 """The middle key switch fused with the plaintext multiply-accumulate
 (Algorithm 2, lines 8-14 in one kernel: the rotated products exist only in
 registers) against the oracle's Algorithm 2 and against the unfused kernels
-(packed keys run the separate key-switch and MAC launches), bit for bit,
+(more accumulators than a fused launch holds run the separate key-switch and
+MAC launches), with packed keys and plaintexts as well, bit for bit,
 alone and as the items of a batch sharing every key.  The splits cover one
 and several fused launches (more than 16 terms), a middle step of one
 ((n1, 1, n3) runs as (1, n1, n3)), and more accumulators than one fused
@@ -78,8 +79,11 @@ def test_fused_middle_layer_equals_oracle_and_unfused(case, split):
     alone = _single(c, split, dpts, dkeys, dct)
     assert np.array_equal(alone, ref)
     P = gpu_params(c["prm"])
-    unfused = _single(c, split, dpts, {r: H.ckks_pack(P, k) for r, k in dkeys.items()}, dct)
-    assert np.array_equal(unfused, alone)
+    pkeys = {r: H.ckks_pack(P, k) for r, k in dkeys.items()}
+    ppts = [None if f is None else H.ckks_pack(P, f) for f in dpts]
+    assert np.array_equal(_single(c, split, dpts, pkeys, dct), alone)
+    assert np.array_equal(_single(c, split, ppts, pkeys, dct), alone)
+    assert np.array_equal(_single(c, split, ppts, dkeys, dct), alone)
     pair = _shared_pair(c, split, dpts, dkeys, dct)
     assert np.array_equal(pair[0], alone) and np.array_equal(pair[1], alone)
     z = o.decrypt_slots(alone, c["delta"] * c["delta"] / c["prm"].q[c["level"]])
