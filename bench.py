@@ -41,8 +41,7 @@ PROFILE_VALU = os.path.join(PROFILES, "valu_counters_th444_n16_l24_d64.md")
 PROFILE_LTS = 60  # TH-BSGS LTs in those runs: `--profile-only --only th --steps 10 --warmup 50`
 # The kernel (and template instance) behind each timed kernel id in one
 # TH-BSGS (4,4,4) step at level 24, as rocprofv3 names it.
-TH444_KERNEL = {"ptmac": "mac_kernel<4, false>", "keyswitch_gather": "ks_gather_kernel<false, 3>",
-                "ksmac": "ksmac_kernel<4, 3>"}
+TH444_KERNEL = {"keyswitch_gather": "ks_gather_kernel<false, 3>", "ksmac": "ksmac_kernel<4, 3, false, false>"}
 
 
 def parse():
