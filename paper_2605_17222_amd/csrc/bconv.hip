@@ -27,6 +27,7 @@ __global__ void __launch_bounds__(kThreads)
   const BConvPlan* __restrict__ plan = a.plan[item];
   const uint64_t* __restrict__ src = a.src[item];
   uint64_t* __restrict__ dst = a.dst[item];
+  const uint64_t* __restrict__ aux = a.aux[item];
   const int shift = a.dst_shift[item];
   const size_t n = (size_t)1 << log_n;
   const size_t p = (size_t)blockIdx.x * kThreads + threadIdx.x;
@@ -75,18 +76,25 @@ __global__ void __launch_bounds__(kThreads)
     }
     for (int m = m0; m < m1; ++m) {
       const int di = plan->dst[m];
-      dst[(size_t)(di - shift) * n + p] = redc(dot_split30<NS>(y0, y1, cst2[m - m0]), qd[m - m0][0], qd[m - m0][1]);
+      const size_t o = (size_t)(di - shift) * n + p;
+      const uint64_t q = qd[m - m0][0];
+      uint64_t v = redc(dot_split30<NS>(y0, y1, cst2[m - m0]), q, qd[m - m0][1]);
+      if (aux) v = shoup(aux[o] - v + q, plan->sinv[m], plan->sinv_sh[m], q);
+      dst[o] = v;
     }
     return;
   }
   for (int m = m0; m < m1; ++m) {
     const int di = plan->dst[m];
+    const size_t o = (size_t)(di - shift) * n + p;
     const uint64_t q = qd[m - m0][0], qn = qd[m - m0][1];
     const uint64_t* c = cst[m - m0];
     U128 acc = mul_wide(y[0], c[0]);
 #pragma unroll
     for (int j = 1; j < NS; ++j) add128(acc, mul_wide(y[j], c[j]));
-    dst[(size_t)(di - shift) * n + p] = redc(acc, q, qn);
+    uint64_t v = redc(acc, q, qn);
+    if (aux) v = shoup(aux[o] - v + q, plan->sinv[m], plan->sinv_sh[m], q);
+    dst[o] = v;
   }
 }
 

@@ -98,7 +98,7 @@ struct LimbRange {
   int pad;
 };
 
-constexpr int kMaxRanges = 16;
+constexpr int kMaxRanges = 32;
 struct NttArgs {
   int nr = 0;
   LimbRange r[kMaxRanges];
@@ -113,6 +113,9 @@ struct BConvArgs {
   const BConvPlan* plan[kMaxConv];
   const uint64_t* src[kMaxConv];  // source limb j at src + j N
   uint64_t* dst[kMaxConv];        // destination limb m at dst + (plan.dst[m] - dst_shift) N
+  // division epilogue (null: none): dst = (aux - conv) * plan.sinv, aux laid
+  // out like dst (the kept limbs in the coefficient domain)
+  const uint64_t* aux[kMaxConv];
   int dst_shift[kMaxConv];
   int limbs_moved;                // sum over items of ns + nd (timing only)
   int max_nd;                     // largest nd over the items (sets the grid's destination chunks)

@@ -92,11 +92,13 @@ struct BConvBatch {
     memset(&a, 0, sizeof(a));
     items = 0;
   }
-  void add(const BConvPlan* plan, int ns_item, int nd, const uint64_t* src, uint64_t* dst, int shift) {
+  void add(const BConvPlan* plan, int ns_item, int nd, const uint64_t* src, uint64_t* dst, int shift,
+           const uint64_t* aux = nullptr) {
     if (items == kMaxConv) flush();
     a.plan[items] = plan;
     a.src[items] = src;
     a.dst[items] = dst;
+    a.aux[items] = aux;
     a.dst_shift[items] = shift;
     a.limbs_moved += ns_item + nd;
     a.max_nd = std::max(a.max_nd, nd);
@@ -219,6 +221,65 @@ void divide(Run& R, DivKind kind, const Jobs& xs) {
       const BConvPlan* plan = plan_of(level);
       const uint64_t* keep = kind == DIV_RESCALE ? xs[t].in : xs[t].in + (size_t)a * N;
       fwd.add(range(xs[t].out, xs[t].out, a, nout_of(level), keep, nullptr, plan->sinv, plan->sinv_sh));
+    }
+  }
+  R.ws.reset(mark);
+}
+
+// ModDown (eq. (4)) and then Decompose (Fig. 1) of level-l PQ polynomials
+// (Algorithm 2 lines 6-7 and 15-16) into digits [beta_l][alpha+l+1][N].
+// b' = (b_Q - conv(b_P)) P^-1 is the same polynomial whichever domain the
+// subtraction runs in (the NTT is linear and bijective), so it runs in the
+// coefficient domain: one inverse NTT of all K limbs of b, the conversion
+// P -> Q with the subtraction and scaling as its epilogue (b' in coefficient
+// form), the digits' conversions from b', and one forward NTT of b' (into
+// the digits' own-group limbs) and of the extensions.  The same limb
+// transforms as ModDown then Decompose (ModDown's forward NTT of the
+// conversion and Decompose's inverse NTT of b' become the inverse NTT of
+// b_Q and the forward NTT of b'), in 6 launches instead of 10, each over
+// more limbs.
+void moddown_decompose(Run& R, const Jobs& xs) {
+  const ckks_params* P = R.P;
+  const int a = P->alpha;
+  const size_t N = R.N, mark = R.ws.mark();
+  std::vector<uint64_t*> coef(xs.size()), bq(xs.size());
+  for (size_t t = 0; t < xs.size(); ++t) {
+    coef[t] = R.limbs(P->K(xs[t].level));
+    bq[t] = R.limbs(xs[t].level + 1);
+  }
+  if (R.live()) {
+    {
+      NttBatch inv(R, false);
+      for (size_t t = 0; t < xs.size(); ++t) inv.add(range(xs[t].in, coef[t], 0, P->K(xs[t].level)));
+    }
+    {
+      BConvBatch bc(R, a);
+      for (size_t t = 0; t < xs.size(); ++t)
+        bc.add(P->plan(P->plan_moddown[xs[t].level]), a, xs[t].level + 1, coef[t], bq[t], a, coef[t] + (size_t)a * N);
+    }
+    {
+      int gmax = 1;
+      for (size_t t = 0; t < xs.size(); ++t) gmax = std::max(gmax, std::min(a, xs[t].level + 1));
+      BConvBatch bc(R, gmax);
+      for (size_t t = 0; t < xs.size(); ++t) {
+        const int level = xs[t].level, K = P->K(level);
+        for (int b = 0; b < P->beta(level); ++b) {
+          const int lo = b * a, hi = std::min(lo + a - 1, level), g = hi - lo + 1;
+          bc.add(P->plan(P->plan_decomp[(size_t)level * P->beta_max + b]), g, K - g, bq[t] + (size_t)lo * N,
+                 xs[t].out + (size_t)b * K * N, 0);
+        }
+      }
+    }
+    NttBatch fwd(R, true);
+    for (size_t t = 0; t < xs.size(); ++t) {
+      const int level = xs[t].level, K = P->K(level);
+      for (int b = 0; b < P->beta(level); ++b) {
+        const int lo = b * a, hi = std::min(lo + a - 1, level);
+        uint64_t* d = xs[t].out + (size_t)b * K * N;
+        fwd.add(range(bq[t] + (size_t)lo * N, d + (size_t)(a + lo) * N, a + lo, hi - lo + 1));
+        fwd.add(range(d, d, 0, a + lo));
+        fwd.add(range(d + (size_t)(a + hi + 1) * N, d + (size_t)(a + hi + 1) * N, a + hi + 1, K - (a + hi + 1)));
+      }
     }
   }
   R.ws.reset(mark);
@@ -545,7 +606,8 @@ struct ThItem {
   std::vector<char> used_m, used_i, mid_i, used_k;
   bool need_d0 = false;
   // buffers
-  std::vector<uint64_t*> Dg, A, B, U0, U1, tmpQ, tmpK, Dk;
+  std::vector<uint64_t*> Dg, A, B, U0, U1, Dk;
+  bool fused = false;  // lines 8-14 in the fused kernel (fuse_middle)
   uint64_t* acc0 = nullptr;  // (c0, c1) of lines 12-18 at PQ
   uint64_t* acc1 = nullptr;
   long giant(const ckks_params* P, int k) const {
@@ -561,17 +623,12 @@ struct ThItem {
 // to kMaxDig digit sets, but the rotation products it stores and the MAC
 // reads back cost more (measured: 32 same-shape LTs 738 -> 768 LT/s, the
 // 128-item ragged batch 1346 -> 1430 LT/s when fused).
-std::vector<char> fuse_middle(const ckks_params* P, const std::vector<ThItem>& items) {
-  std::vector<char> out(items.size(), 0);
-  for (size_t t = 0; t < items.size(); ++t) {
-    const ThItem& it = items[t];
-    if (P->n % kKsMacAlign) continue;
-    int nk = it.kdir < 0 ? 1 : 0, nterms = 0;
-    for (int k = 0; k < it.n3; ++k) nk += (k == it.kdir || it.used_k[k]) ? 1 : 0;
-    for (int m = 0; m < it.n1 * it.n2; ++m) nterms += it.used_m[m] ? 1 : 0;
-    out[t] = (nk <= kMaxMacK && nterms > 0) ? 1 : 0;
-  }
-  return out;
+bool fuse_middle(const ckks_params* P, const ThItem& it) {
+  if (P->n % kKsMacAlign) return false;
+  int nk = it.kdir < 0 ? 1 : 0, nterms = 0;
+  for (int k = 0; k < it.n3; ++k) nk += (k == it.kdir || it.used_k[k]) ? 1 : 0;
+  for (int m = 0; m < it.n1 * it.n2; ++m) nterms += it.used_m[m] ? 1 : 0;
+  return nk <= kMaxMacK && nterms > 0;
 }
 
 // Lines 8-14 of one item in one kernel: every used term m = n1 j + i is
@@ -660,7 +717,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
   const ckks_params* P = R.P;
   // Plan every item and take its buffers.
   for (ThItem& it : items) {
-    const int K = P->K(it.level), beta = P->beta(it.level), inner = it.n1 * it.n2, Lq = it.level + 1;
+    const int K = P->K(it.level), beta = P->beta(it.level), inner = it.n1 * it.n2;
     it.used_m.assign(inner, 0);
     it.used_i.assign(it.n1, 0);
     it.mid_i.assign(it.n1, 0);
@@ -681,28 +738,24 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     it.Dg.assign(it.n1, nullptr);
     it.A.assign(inner, nullptr);
     it.B.assign(inner, nullptr);
-    it.tmpQ.assign(it.n1, nullptr);
+    it.fused = fuse_middle(P, it);
     for (int i = 0; i < it.n1; ++i)
       if ((i == 0 && it.need_d0) || (i > 0 && it.mid_i[i])) it.Dg[i] = R.limbs((size_t)beta * K);
+    // the inner layer's products (m < n1); the middle layer's only when they
+    // are materialised (not fused)
     for (int m = 1; m < inner; ++m)
-      if (it.used_m[m] || (m < it.n1 && it.used_i[m])) {
+      if ((m < it.n1 && (it.used_m[m] || it.used_i[m])) || (m >= it.n1 && it.used_m[m] && !it.fused)) {
         it.A[m] = R.limbs(K);
         it.B[m] = R.limbs(K);
       }
-    for (int i = 1; i < it.n1; ++i)
-      if (it.mid_i[i]) it.tmpQ[i] = R.limbs(Lq);
     it.U0.assign(it.n3, nullptr);
     it.U1.assign(it.n3, nullptr);
-    it.tmpK.assign(it.n3, nullptr);
     it.Dk.assign(it.n3, nullptr);
     for (int k = 0; k < it.n3; ++k) {
       if (k != it.kdir && !it.used_k[k]) continue;
       it.U0[k] = R.limbs(K);
       it.U1[k] = R.limbs(K);
-      if (k != it.kdir) {
-        it.tmpK[k] = R.limbs(Lq);
-        it.Dk[k] = R.limbs((size_t)beta * K);
-      }
+      if (k != it.kdir) it.Dk[k] = R.limbs((size_t)beta * K);
     }
     if (it.kdir >= 0) {
       it.acc0 = it.U0[it.kdir];
@@ -731,26 +784,21 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
   }
   // Lines 6-7: d_i = Decompose(ModDown(b_i)), every i at once.
   {
-    Jobs md, dc;
+    Jobs mdc;
     for (ThItem& it : items)
       for (int i = 1; i < it.n1; ++i)
-        if (it.mid_i[i]) {
-          md.push_back({it.level, it.B[i], it.tmpQ[i]});
-          dc.push_back({it.level, it.tmpQ[i], it.Dg[i]});
-        }
-    divide(R, DIV_MODDOWN, md);
-    decompose(R, dc);
+        if (it.mid_i[i]) mdc.push_back({it.level, it.B[i], it.Dg[i]});
+    moddown_decompose(R, mdc);
   }
   // Lines 8-14 fused where fuse_middle allows (see ksmac below); for the
   // other items the middle key switch runs first.
-  std::vector<char> fused = fuse_middle(P, items);
   // Lines 8-11: middle rotations by s n1 j share d_i; each middle key is read
   // once per launch for all digit sets.
   {
     std::vector<KsTask> tasks;
     for (size_t t = 0; t < items.size(); ++t) {
       ThItem& it = items[t];
-      if (fused[t]) continue;
+      if (it.fused) continue;
       for (int j = 1; j < it.n2; ++j)
         for (int i = 0; i < it.n1; ++i) {
           const int m = it.n1 * j + i;
@@ -772,7 +820,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
     for (int k = 0; k < it.n3; ++k)
       if (k == it.kdir || it.used_k[k]) kk.push_back(k);
     if (it.kdir < 0) kk.push_back(-1);
-    if (fused[t]) {
+    if (it.fused) {
       ksmac(R, it, kk);
       continue;
     }
@@ -805,15 +853,11 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
   // (item, k) at once, then per item one gather kernel adds
   // phi_G(u0 + x), phi_G(y) of all its k into (c0, c1).
   {
-    Jobs md, dc;
+    Jobs mdc;
     for (ThItem& it : items)
       for (int k = 0; k < it.n3; ++k)
-        if (k != it.kdir && it.used_k[k]) {
-          md.push_back({it.level, it.U1[k], it.tmpK[k]});
-          dc.push_back({it.level, it.tmpK[k], it.Dk[k]});
-        }
-    divide(R, DIV_MODDOWN, md);
-    decompose(R, dc);
+        if (k != it.kdir && it.used_k[k]) mdc.push_back({it.level, it.U1[k], it.Dk[k]});
+    moddown_decompose(R, mdc);
     for (ThItem& it : items) {
       std::vector<int> kk;
       for (int k = 0; k < it.n3; ++k)
