@@ -20,7 +20,10 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kChunk = 27;  // destination limbs per workgroup (grid.z splits the rest)
 
-template <int NS>
+// S30: every plan of the launch is split30 (all its primes below 2^60), so
+// only the 30-bit halves of the y_j are kept (half the registers of the
+// general kernel, which holds the full words for the 128-bit products).
+template <int NS, bool S30>
 __global__ void __launch_bounds__(kThreads)
     bconv_kernel(BConvArgs a, const PrimeDev* __restrict__ primes, int log_n) {
   const int item = blockIdx.y;
@@ -62,17 +65,17 @@ __global__ void __launch_bounds__(kThreads)
   // shorter than alpha) has zeros in the remaining places: every product
   // with them vanishes.
   const int nsi = plan->ns;
-  uint64_t y[NS];
-#pragma unroll
-  for (int j = 0; j < NS; ++j)
-    y[j] = j < nsi ? shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], primes[plan->src[j]].q) : 0;
-  if (plan->split30) {
+  auto yj = [&](int j) -> uint64_t {
+    return j < nsi ? shoup(src[(size_t)j * n + p], plan->hinv[j], plan->hinv_sh[j], primes[plan->src[j]].q) : 0;
+  };
+  if constexpr (S30) {
     // all primes below 2^60: the inner product from 30-bit column sums
     uint32_t y0[NS], y1[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-      y0[j] = (uint32_t)(y[j] & ((1ull << 30) - 1));
-      y1[j] = (uint32_t)(y[j] >> 30);
+      const uint64_t v = yj(j);
+      y0[j] = (uint32_t)(v & ((1ull << 30) - 1));
+      y1[j] = (uint32_t)(v >> 30);
     }
     for (int m = m0; m < m1; ++m) {
       const int di = plan->dst[m];
@@ -84,6 +87,9 @@ __global__ void __launch_bounds__(kThreads)
     }
     return;
   }
+  uint64_t y[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) y[j] = yj(j);
   for (int m = m0; m < m1; ++m) {
     const int di = plan->dst[m];
     const size_t o = (size_t)(di - shift) * n + p;
@@ -101,7 +107,12 @@ __global__ void __launch_bounds__(kThreads)
 template <int NS>
 hipError_t launch_ns(const ckks_params* P, const BConvArgs& a, int items, hipStream_t s) {
   dim3 grid(P->n / kThreads, items, (a.max_nd + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL((bconv_kernel<NS>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  bool s30 = true;
+  for (int i = 0; i < items; ++i) s30 = s30 && P->plan_is_split30(a.plan[i]);
+  if (s30)
+    hipLaunchKernelGGL((bconv_kernel<NS, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+  else
+    hipLaunchKernelGGL((bconv_kernel<NS, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
   return hipGetLastError();
 }
 

@@ -278,6 +278,7 @@ struct ckks_params {
   double* d_enc_tw = nullptr;
   double* d_enc_zinv = nullptr;
   std::vector<std::pair<int, int>> plan_shape;  // host copy of each plan's (ns, nd)
+  std::vector<uint8_t> plan_split30;            // host copy of each plan's split30
   std::vector<int> plan_decomp;        // level * beta_max + b -> plan index
   std::vector<int> plan_moddown, plan_mdrescale, plan_rescale;  // per level
   int beta_max = 0;
@@ -289,5 +290,9 @@ struct ckks_params {
   std::pair<int, int> plan_dims(const ckks::BConvPlan* p) const {
     const ptrdiff_t i = p - d_plans;
     return (i >= 0 && (size_t)i < plan_shape.size()) ? plan_shape[(size_t)i] : std::pair<int, int>(-1, -1);
+  }
+  bool plan_is_split30(const ckks::BConvPlan* p) const {
+    const ptrdiff_t i = p - d_plans;
+    return i >= 0 && (size_t)i < plan_split30.size() && plan_split30[(size_t)i];
   }
 };

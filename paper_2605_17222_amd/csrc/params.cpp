@@ -323,7 +323,10 @@ int params_create(const ckks_params_desc* d, ckks_params** out) {
   if (hipMalloc(&P->d_tw, tw.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_trow, trow.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_primes, pd.size() * sizeof(PrimeDev)) != hipSuccess) return CKKS_E_NOMEM;
-  for (const BConvPlan& pl : plans) P->plan_shape.push_back({pl.ns, pl.nd});
+  for (const BConvPlan& pl : plans) {
+    P->plan_shape.push_back({pl.ns, pl.nd});
+    P->plan_split30.push_back(pl.split30 ? 1 : 0);
+  }
   if (hipMalloc(&P->d_plans, plans.size() * sizeof(BConvPlan)) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_enc_perm, perm.size() * sizeof(int)) != hipSuccess) return CKKS_E_NOMEM;
   if (hipMalloc(&P->d_enc_tw, etw.size() * 8) != hipSuccess) return CKKS_E_NOMEM;
