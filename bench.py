@@ -898,6 +898,19 @@ def main():
     breakdown = {k: {"launches_per_step": v[0] / probe_steps, "ms_per_step": round(v[1] / probe_steps, 4),
                      "GB_per_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] else None}
                  for k, v in prof.items() if v[0]}
+    # Algorithm 2's key-switch phases together (lines 4-5 in the inner
+    # key-switch kernel, 8-14 fused with the multiply-accumulate, 17-18 in
+    # the gather kernel): their kernels' algorithmic bytes (each operand
+    # once, the library's own count) over their summed kernel time
+    ks_names = [k for k in ("keyswitch", "ksmac", "keyswitch_gather") if k in prof and prof[k][0]]
+    ks_bytes = sum(prof[k][2] for k in ks_names) / probe_steps
+    ks_ms = sum(prof[k][1] for k in ks_names) / probe_steps
+    keyswitch_phases = {"kernels": ks_names, "bytes_per_step": round(ks_bytes),
+                        "ms_per_step": round(ks_ms, 4),
+                        "GB_per_s": round(ks_bytes / (ks_ms * 1e-3) / 1e9, 1) if ks_ms else None,
+                        "frac_of_hbm_peak": round(ks_bytes / (ks_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ks_ms else None,
+                        "note": "the key-switch kernels of one LT together: algorithmic bytes (each operand once) "
+                                "over their summed time, from the pass with every kernel timed"}
     comp = compulsory_bytes(prm, level, th_split, "th")
     whole = {"compulsory_bytes_per_lt": comp, "ms_per_lt": round(ms_step, 4),
              "GB_per_s": round(comp / (ms_step * 1e-3) / 1e9, 1),
@@ -949,6 +962,7 @@ def main():
         "th_vs_bsgs_speedup": round(bs_ms / ms_step, 3),
         "workspace_bytes": ws_bytes,
         "roofline": roofline,
+        "keyswitch_phases": keyswitch_phases,
         "valu": valu,
         "kernels": breakdown,
         "host_enqueue_ms_per_step": round(enq_main / args.steps, 4),

@@ -111,13 +111,13 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
     // Measured on one MI355X (python -m paper_2605_17222_amd.calibrate: 120
     // banded LTs at N = 2^16, levels 8, 16, 24, 16..256 diagonals): the BConv
     // rate from that kernel's own time, the other three fitted to the rest;
-    // mean prediction error 5.4% (max 26%), the pick 2.8% slower than the
-    // fastest timed split of its group on average (at most 12%; identical
+    // mean prediction error 6.3% (max 20%), the pick 2.2% slower than the
+    // fastest timed split of its group on average (at most 7.4%; identical
     // runs of one split differ by up to 2%).
-    r.ntt_limb_s = 3.53e-7;
-    r.bconv_product_s = 0.589e-12;
-    r.hbm_bytes_per_s = 5.13e12;
-    r.layer_s = 111.8e-6;
+    r.ntt_limb_s = 1.82e-7;
+    r.bconv_product_s = 0.650e-12;
+    r.hbm_bytes_per_s = 4.69e12;
+    r.layer_s = 97.0e-6;
   }
   if (algo == CKKS_LT_DH_BSGS) {  // Algorithm 2 with an empty inner layer
     n3 = n2;
