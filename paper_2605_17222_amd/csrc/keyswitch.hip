@@ -670,6 +670,14 @@ __global__ void __launch_bounds__(kThreads)
         ksmac_body<NK, MB, true, PK, PF, true>(a, pr, l, p, n, log_n, alpha);
         return;
       }
+      // With more than 6 accumulators, three bodies in one kernel make the
+      // compiler keep the whole argument block in per-lane scratch; the wide
+      // limbs of the FP64 path (primes between 2^40 and 2^46) then take the
+      // integer body, which serves any prime.
+      if constexpr (NK > 6) {
+        ksmac_body<NK, MB, false, PK, PF, false>(a, pr, l, p, n, log_n, alpha);
+        return;
+      }
     }
     ksmac_body<NK, MB, true, PK, PF, false>(a, pr, l, p, n, log_n, alpha);
   } else {

@@ -88,3 +88,39 @@ def test_fused_middle_layer_equals_oracle_and_unfused(case, split):
     assert np.array_equal(pair[0], alone) and np.array_equal(pair[1], alone)
     z = o.decrypt_slots(alone, c["delta"] * c["delta"] / c["prm"].q[c["level"]])
     assert np.abs(z - W.matvec(c["diags"], c["v"])).max() <= 5e-3
+
+
+def test_fused_many_accumulators_every_limb_kind_packed():
+    """A fused launch with 8 accumulators ((1, 2, 8)) over a chain holding
+    all three kinds of limb: integer-path primes (50 bits), FP64-path primes
+    stored at full width (42 and 44 bits) and narrow ones (35 bits, packed
+    in 5 bytes).  With this many accumulators the packed kernels run the
+    wide FP64-path limbs on the integer body; every layout equals the
+    oracle's Algorithm 2 bit for bit."""
+    log("fused, 8 accumulators, mixed limb kinds")
+    two_n = 1 << 13
+    p50 = W.ntt_primes(50, 3, two_n)
+    prm = W.Params(log_n=12, q=(p50[0], W.ntt_primes(42, 1, two_n)[0], W.ntt_primes(35, 1, two_n)[0],
+                                W.ntt_primes(44, 1, two_n)[0]),
+                   p=(p50[1], p50[2]), dnum=2, log_delta=30, h=64)
+    o = O.Oracle(prm)
+    o.keygen(29)
+    delta = 2.0 ** prm.log_delta
+    level = prm.max_level
+    split = (1, 2, 8)
+    diags = W.banded_diagonals(41, prm.slots, range(16))
+    ct = o.encrypt(level, W.input_vector(41, prm.slots), delta, seed=43)
+    pts = o.th_plaintexts(diags, *split, delta)
+    keys = {r: o.rotkey(r) for r in W.th_rotations(*split)}
+    ref = o.lt_th(level, ct, split, pts, keys)
+    c = dict(prm=prm, level=level, delta=delta)
+    dpts = [None if f is None else H.to_device(f) for f in pts]
+    dkeys = {r: H.to_device(k) for r, k in keys.items()}
+    dct = [H.to_device(ct[0]), H.to_device(ct[1])]
+    assert np.array_equal(_single(c, split, dpts, dkeys, dct), ref)
+    P = gpu_params(prm)
+    pkeys = {r: H.ckks_pack(P, k) for r, k in dkeys.items()}
+    ppts = [None if f is None else H.ckks_pack(P, f) for f in dpts]
+    assert np.array_equal(_single(c, split, dpts, pkeys, dct), ref)
+    assert np.array_equal(_single(c, split, ppts, pkeys, dct), ref)
+    assert np.array_equal(_single(c, split, ppts, dkeys, dct), ref)
