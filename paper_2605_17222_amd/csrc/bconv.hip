@@ -18,14 +18,16 @@ namespace ckks {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 27;  // destination limbs per workgroup (grid.z splits the rest)
+constexpr int kChunk = 27;     // most destination limbs per workgroup (grid.z splits the rest)
+constexpr int kMinWgs = 2048;  // workgroups a launch is split to reach (8 per CU)
+constexpr int kMinChunk = 6;   // fewest destination limbs per workgroup when splitting for that
 
 // S30: every plan of the launch is split30 (all its primes below 2^60), so
 // only the 30-bit halves of the y_j are kept (half the registers of the
 // general kernel, which holds the full words for the 128-bit products).
 template <int NS, bool S30>
 __global__ void __launch_bounds__(kThreads)
-    bconv_kernel(BConvArgs a, const PrimeDev* __restrict__ primes, int log_n) {
+    bconv_kernel(BConvArgs a, const PrimeDev* __restrict__ primes, int log_n, int chunk) {
   const int item = blockIdx.y;
   const BConvPlan* __restrict__ plan = a.plan[item];
   const uint64_t* __restrict__ src = a.src[item];
@@ -37,9 +39,9 @@ __global__ void __launch_bounds__(kThreads)
   // m1 <= m0 when this item has fewer destination limbs than the launch's
   // widest item: then the chunk is empty (cnt = 0) and only the shared
   // staging below runs (with nothing to stage).
-  const int m0 = blockIdx.z * kChunk;
-  const int m1 = max(m0, min(plan->nd, m0 + kChunk));
-  const int cnt = m1 - m0;  // 0 .. kChunk
+  const int m0 = blockIdx.z * chunk;
+  const int m1 = max(m0, min(plan->nd, m0 + chunk));
+  const int cnt = m1 - m0;  // 0 .. chunk <= kChunk
 
   // The chunk's constants and primes, staged once per workgroup: read from
   // global memory inside the destination loop they would make every
@@ -106,13 +108,22 @@ __global__ void __launch_bounds__(kThreads)
 
 template <int NS>
 hipError_t launch_ns(const ckks_params* P, const BConvArgs& a, int items, hipStream_t s) {
-  dim3 grid(P->n / kThreads, items, (a.max_nd + kChunk - 1) / kChunk);
+  // Destination chunks: at most kChunk limbs each; a launch with few
+  // workgroups (few conversions) is split further, down to kMinChunk limbs
+  // per chunk, until it has about kMinWgs (each chunk converts its sources
+  // again, a small cost against the destinations' inner products).
+  const int wgs = P->n / kThreads * items;
+  int nch = (a.max_nd + kChunk - 1) / kChunk;
+  nch = std::max(nch, std::min((kMinWgs + wgs - 1) / wgs, (a.max_nd + kMinChunk - 1) / kMinChunk));
+  const int chunk = (a.max_nd + nch - 1) / nch;
+  nch = (a.max_nd + chunk - 1) / chunk;
+  dim3 grid(P->n / kThreads, items, nch);
   bool s30 = true;
   for (int i = 0; i < items; ++i) s30 = s30 && P->plan_is_split30(a.plan[i]);
   if (s30)
-    hipLaunchKernelGGL((bconv_kernel<NS, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+    hipLaunchKernelGGL((bconv_kernel<NS, true>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, chunk);
   else
-    hipLaunchKernelGGL((bconv_kernel<NS, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n);
+    hipLaunchKernelGGL((bconv_kernel<NS, false>), grid, dim3(kThreads), 0, s, a, P->d_primes, P->log_n, chunk);
   return hipGetLastError();
 }
 
