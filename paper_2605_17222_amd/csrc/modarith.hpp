@@ -84,9 +84,10 @@ __host__ __device__ __forceinline__ uint64_t barrett128(U128 x, uint64_t q, uint
 // |l| <= ulp(h)/2 <= 2^45, so it is an integer below 2^53 and the FMA that
 // forms it is exact.
 
-// x < 2^53 as a double.
+// x < 2^52 as a double: the bits of 2^52 with x as the significand are the
+// double 2^52 + x (one OR into the high word), and subtracting 2^52 is exact.
 __host__ __device__ __forceinline__ double u64_to_d(uint64_t x) {
-  return fma((double)(uint32_t)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+  return __builtin_bit_cast(double, x | 0x4330000000000000ull) - 4503599627370496.0;
 }
 
 __host__ __device__ __forceinline__ double fp_mulmod(double x, double w, double wq, double q) {
@@ -114,14 +115,13 @@ __host__ __device__ __forceinline__ double fp_reduce(double x, double q, double 
   return fma(-rint(x * qinv), q, x);
 }
 
-// |x| < 2^52 -> canonical residue in [0, q) as uint64.
+// |x| < 2^52 -> canonical residue in [0, q) as uint64 (the residue r is an
+// integer below 2^52, so 2^52 + r is exact and its significand is r).
 __host__ __device__ __forceinline__ uint64_t fp_canon(double x, double q, double qinv) {
   double r = fp_reduce(x, q, qinv);
   r = r < 0 ? r + q : r;
   r = r >= q ? r - q : r;
-  const double hi = floor(r * (1.0 / 4294967296.0));
-  const double lo = fma(-hi, 4294967296.0, r);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+  return __builtin_bit_cast(uint64_t, r + 4503599627370496.0) & ((1ull << 52) - 1);
 }
 
 // sum_j y_j c_j for NS <= 16 terms with y_j, c_j < 2^60, from 30-bit halves
