@@ -584,8 +584,10 @@ __device__ __forceinline__ void ksmac_body(const KsMacArgs& a, const PrimeDev& p
         }
         double addv = u64_to_d(cur.a);
         if (a.pscaled[m]) addv = fp_mulmod(addv, pm, pmq, qd);
-        av = fp_reduce(u + addv, qd, qi);
-        bv = fp_reduce(v, qd, qi);
+        // not reduced: |u| < 0.6 beta q <= 2.4 q and |addv| < q, within the
+        // 4 q that fp_mulmod_var takes for its first operand
+        av = u + addv;
+        bv = v;
       }
 #pragma unroll
       for (int k = 0; k < NK; ++k) {

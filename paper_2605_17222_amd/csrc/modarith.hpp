@@ -98,11 +98,12 @@ __host__ __device__ __forceinline__ double fp_mulmod(double x, double w, double 
 }
 
 // x * y mod q for two data operands (no precomputed quotient), q < 2^46,
-// |x|, |y| <= q: h = fl(x y) and l = x y - h (exact, |l| <= ulp(h)/2 <=
-// 2^38) are the two-product; h/q < q < 2^46, so t = rint(h fl(1/q)) is within
-// 1/2 + 2^-5 of h/q and h - t q is an integer of magnitude below
-// (1/2 + 2^-5) q: the FMA that forms it is exact; the result h - t q + l is
-// congruent to x y and below 0.6 q + 2^38 in magnitude, exact as well.
+// |x| <= 4 q, |y| <= q: h = fl(x y) and l = x y - h (exact, |l| <= ulp(h)/2
+// <= 2^-53 4 q^2 < 2^-5 q) are the two-product; h/q < 4 q < 2^48, so
+// t = rint(h fl(1/q)) is within 1/2 + 2^-4 of h/q and h - t q is an integer
+// of magnitude below (1/2 + 2^-4) q: the FMA that forms it is exact; the
+// result h - t q + l is congruent to x y and below 0.6 q in magnitude, exact
+// as well.
 __host__ __device__ __forceinline__ double fp_mulmod_var(double x, double y, double q, double qinv) {
   const double h = x * y;
   const double l = fma(x, y, -h);
