@@ -946,7 +946,7 @@ def main():
                 "kernels": {k: {f: v[f] for f in ("valu_issue_frac", "valu_active_per_wave_cycle",
                                                   "wait_per_wave_cycle", "valu_insts_per_wave")}
                             for k, v in valu_blk["kernels"].items()
-                            if k.startswith(("ntt_pass", "bconv_kernel", "ks_", "mac_kernel"))}}
+                            if k.startswith(("ntt_pass", "bconv_kernel", "ks_", "ksmac_kernel", "mac_kernel"))}}
     out = {
         "metric": METRIC, "value": round(lt_s, 2), "unit": "LT/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
