@@ -117,7 +117,7 @@ struct BConvArgs {
   // out like dst (the kept limbs in the coefficient domain)
   const uint64_t* aux[kMaxConv];
   int dst_shift[kMaxConv];
-  int limbs_moved;                // sum over items of ns + nd (timing only)
+  int limbs_moved;                // sum over items of ns + nd, + nd with aux (timing only)
   int max_nd;                     // largest nd over the items (sets the grid's destination chunks)
 };
 

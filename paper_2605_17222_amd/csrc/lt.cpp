@@ -100,7 +100,7 @@ struct BConvBatch {
     a.dst[items] = dst;
     a.aux[items] = aux;
     a.dst_shift[items] = shift;
-    a.limbs_moved += ns_item + nd;
+    a.limbs_moved += ns_item + nd + (aux ? nd : 0);
     a.max_nd = std::max(a.max_nd, nd);
     ++items;
   }
@@ -790,7 +790,7 @@ void lt_th(Run& R, std::vector<ThItem>& items) {
         if (it.mid_i[i]) mdc.push_back({it.level, it.B[i], it.Dg[i]});
     moddown_decompose(R, mdc);
   }
-  // Lines 8-14 fused where fuse_middle allows (see ksmac below); for the
+  // Lines 8-14 fused where fuse_middle allows (ksmac above); for the
   // other items the middle key switch runs first.
   // Lines 8-11: middle rotations by s n1 j share d_i; each middle key is read
   // once per launch for all digit sets.
