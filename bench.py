@@ -41,6 +41,9 @@ PROFILE_VALU = os.path.join(PROFILES, "valu_counters_th444_n16_l24_d64.md")
 PROFILE_LTS = 60  # TH-BSGS LTs in those runs: `--profile-only --only th --steps 10 --warmup 50`
 # The kernel (and template instance) behind each timed kernel id in one
 # TH-BSGS (4,4,4) step at level 24, as rocprofv3 names it.
+# The library's kernels of Algorithm 2's key-switch phases (lines 4-5, 8-14
+# fused with the multiply-accumulate, 17-18)
+KEYSWITCH_KERNELS = ("keyswitch", "ksmac", "keyswitch_gather")
 TH444_KERNEL = {"keyswitch_gather": "ks_gather_kernel<false, 3>", "ksmac": "ksmac_kernel<4, 3, false, false>"}
 
 
@@ -902,7 +905,7 @@ def main():
     # key-switch kernel, 8-14 fused with the multiply-accumulate, 17-18 in
     # the gather kernel): their kernels' algorithmic bytes (each operand
     # once, the library's own count) over their summed kernel time
-    ks_names = [k for k in ("keyswitch", "ksmac", "keyswitch_gather") if k in prof and prof[k][0]]
+    ks_names = [k for k in KEYSWITCH_KERNELS if k in prof and prof[k][0]]
     ks_bytes = sum(prof[k][2] for k in ks_names) / probe_steps
     ks_ms = sum(prof[k][1] for k in ks_names) / probe_steps
     keyswitch_phases = {"kernels": ks_names, "bytes_per_step": round(ks_bytes),

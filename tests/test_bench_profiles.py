@@ -21,3 +21,17 @@ def test_profile_summaries_name_the_benchmarked_kernels():
         assert name in valu["kernels"], name
     # the trace covers the number of LTs the bench divides by
     assert trace["kernels"][bench.TH444_KERNEL["ksmac"]]["calls"] == bench.PROFILE_LTS
+
+
+def test_profile_summaries_were_taken_from_the_current_sources():
+    """Every summary the bench reads carries the digest of the library
+    sources it was profiled from; a committed tree keeps them in step (the
+    bench drops counter figures whose digest does not match)."""
+    for path in (bench.PROFILE_TRACE, bench.PROFILE_HBM, bench.PROFILE_VALU):
+        assert profiling.current_block(path) is not None, path
+
+
+def test_keyswitch_phase_kernels_are_library_kernels():
+    import paper_2605_17222_amd as H
+    for name in bench.KEYSWITCH_KERNELS:
+        assert name in H.KERNELS, name
