@@ -550,8 +550,8 @@ int ckks_th_traffic_model(int log_n, int level, int alpha, int n1, int n2, int n
  * the automorphism gather, the gather form of the key switch that adds
  * every outer rotation into the accumulator, plaintext encoding, and the
  * middle key switch fused with the multiply-accumulate (Algorithm 2, lines
- * 8-14, used for TH-BSGS items with resident unpacked plaintexts and keys
- * and at most 8 accumulators). */
+ * 8-14, used for every TH-BSGS item with at most 8 accumulators, keys and
+ * plaintexts plain or packed, plaintexts resident or encoded on the fly). */
 #define CKKS_KERNEL_NTT_FWD_COL 0
 #define CKKS_KERNEL_NTT_FWD_ROW 1
 #define CKKS_KERNEL_NTT_INV_ROW 2
