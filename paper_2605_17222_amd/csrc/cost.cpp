@@ -158,11 +158,11 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
   // Words moved per coefficient position by the HBM-bound kernels as this
   // library schedules one LT: a key (2 beta K words at this level) is read
   // once per launch for every digit set that uses it (up to 8 digit sets per
-  // launch).  With at most 8 accumulators the middle key switch runs fused
-  // with the multiply-accumulate (lines 8-14 in one kernel per 16 terms):
-  // each middle key, digit set and add read once, the rotation products
-  // never stored; otherwise every product is written once and read once by
-  // the MAC.
+  // launch).  With at most 4 accumulators, or at most 8 and terms that fit
+  // one launch, the middle key switch runs fused with the multiply-
+  // accumulate (lines 8-14 in one kernel per 16 terms): each middle key,
+  // digit set and add read once, the rotation products never stored;
+  // otherwise every product is written once and read once by the MAC.
   const double keyw = 2.0 * beta * K;
   double words = 0;
   int layers = 0;
@@ -171,7 +171,7 @@ int ckks_lt_predict(int log_n, int level, int alpha, int algo, int n1, int n2, i
       words += beta * K + (n1 - 1) * keyw + (n1 - 1) * 2.0 * K + Lq;
       ++layers;
     }
-    if (n2 > 1 && n3 <= 8) {
+    if (n2 > 1 && n3 <= 8 && (n3 <= 4 || n1 * n2 <= 16)) {
       // launches of 16 terms, ordered by middle step: each launch reads the
       // digit sets and adds of its terms (up to 16) and each key once, and
       // every launch after the first reads and writes the accumulators

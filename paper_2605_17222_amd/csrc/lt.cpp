@@ -622,13 +622,18 @@ struct ThItem {
 // share keys: the unfused key-switch launch reads a shared key once for up
 // to kMaxDig digit sets, but the rotation products it stores and the MAC
 // reads back cost more (measured: 32 same-shape LTs 738 -> 768 LT/s, the
-// 128-item ragged batch 1346 -> 1430 LT/s when fused).
+// 128-item ragged batch 1346 -> 1430 LT/s when fused).  With more than 4
+// accumulators the fused kernel runs 2-3 waves per SIMD, and every fused
+// launch after the first reads and writes all its accumulators again, so
+// such items run fused only when their terms fit one launch (measured at
+// level 24: (4,32,8) 9.10 -> 8.20 ms and (1,64,8) 5.33 -> 5.02 ms unfused;
+// (1,16,8) 2.05 against 2.08 ms and (1,16,6) 1.53 against 1.66 ms fused).
 bool fuse_middle(const ckks_params* P, const ThItem& it) {
   if (P->n % kKsMacAlign) return false;
   int nk = it.kdir < 0 ? 1 : 0, nterms = 0;
   for (int k = 0; k < it.n3; ++k) nk += (k == it.kdir || it.used_k[k]) ? 1 : 0;
   for (int m = 0; m < it.n1 * it.n2; ++m) nterms += it.used_m[m] ? 1 : 0;
-  return nk <= kMaxMacK && nterms > 0;
+  return nk <= kMaxMacK && nterms > 0 && (nk <= 4 || nterms <= kMaxMacM);
 }
 
 // Lines 8-14 of one item in one kernel: every used term m = n1 j + i is
