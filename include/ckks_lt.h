@@ -495,7 +495,8 @@ typedef struct {
  * Predicted device seconds of one LT with this split and n_diag present
  * diagonals: the operation counts of ckks_lt_cost_model priced with `rates`,
  * plus the words the key-switch and MAC kernels move as this library
- * schedules one LT (TH-BSGS with at most 8 accumulators: the middle key
+ * schedules one LT (TH-BSGS with at most 4 accumulators, or 8 whose terms
+ * fit one fused launch: the middle key
  * switch fused with the multiply-accumulate, the rotation products never
  * stored).  DH-BSGS (n1, n2) is priced as TH-BSGS (1, n1, n2).  The rates
  * can be refitted on a device with `python -m paper_2605_17222_amd.calibrate`.
@@ -550,8 +551,9 @@ int ckks_th_traffic_model(int log_n, int level, int alpha, int n1, int n2, int n
  * the automorphism gather, the gather form of the key switch that adds
  * every outer rotation into the accumulator, plaintext encoding, and the
  * middle key switch fused with the multiply-accumulate (Algorithm 2, lines
- * 8-14, used for every TH-BSGS item with at most 8 accumulators, keys and
- * plaintexts plain or packed, plaintexts resident or encoded on the fly). */
+ * 8-14, used for every TH-BSGS item with at most 4 accumulators, or 8 whose
+ * terms fit one launch; keys and plaintexts plain or packed, plaintexts
+ * resident or encoded on the fly). */
 #define CKKS_KERNEL_NTT_FWD_COL 0
 #define CKKS_KERNEL_NTT_FWD_ROW 1
 #define CKKS_KERNEL_NTT_INV_ROW 2
