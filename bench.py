@@ -623,6 +623,29 @@ def _spearman(a, b):
     return 1 - 6 * sum((x - y) ** 2 for x, y in zip(ra, rb)) / (n * (n * n - 1))
 
 
+def many_diagonals_leg(P, prm, level, steps, warmup, torch, H):
+    """LTs with 512 and 1024 diagonals (resident plaintexts): the
+    autotuner's TH-BSGS split, its DH-BSGS split (no inner layer, run as
+    TH-BSGS (1, n1, n2)), and plain BSGS at its square split.  With this many
+    diagonals the inner hoisting layer pays on this device."""
+    res = {}
+    for n, bsgs in ((512, (32, 16)), (1024, (32, 32))):
+        th, th_pred = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_TH_BSGS, n)
+        dh, dh_pred = H.ckks_lt_autotune(prm.log_n, level, prm.alpha, H.CKKS_LT_DH_BSGS, n)
+        row = {}
+        for name, split, algo in (("th", tuple(th), "th"), ("dh", (1,) + tuple(dh)[:2], "th"),
+                                  ("plain_bsgs", bsgs, "bsgs")):
+            _, ms, _, _, _ = time_lt(P, prm, level, split, algo, steps, warmup, torch, H)
+            row[name] = {"split": list(split), "ms_per_lt": round(ms / steps, 3)}
+            torch.cuda.empty_cache()
+        row["th_vs_plain_bsgs"] = round(row["plain_bsgs"]["ms_per_lt"] / row["th"]["ms_per_lt"], 3)
+        row["th_vs_dh"] = round(row["dh"]["ms_per_lt"] / row["th"]["ms_per_lt"], 3)
+        res["n%d" % n] = row
+    res["note"] = ("level %d, N=2^%d, uniform-residue inputs; each split timed with all of its n1 n2 n3 "
+                   "(TH) or n1 n2 (BSGS) plaintexts present, at least n" % (level, prm.log_n))
+    return res
+
+
 def split_sweep_leg(P, prm, level, steps, warmup, torch, H):
     """Every split of SWEEP_SPLITS timed (events over `steps` LTs after
     `warmup`), priced by the library's predictor (ckks_lt_predict) and by the
@@ -1001,6 +1024,8 @@ def main():
     if not args.no_sweep:
         out["split_sweep"] = split_sweep_leg(P, prm, level, 10, 20, torch, H)
         print("split sweep done", flush=True, file=sys.stderr)
+        out["many_diagonals"] = many_diagonals_leg(P, prm, level, 5, 5, torch, H)
+        print("many-diagonals leg done", flush=True, file=sys.stderr)
     if not args.no_chain:
         out["dft_chain"] = chain_leg(P, prm, 10, torch, H)
         print("chain leg done", flush=True, file=sys.stderr)
